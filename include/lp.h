@@ -1,0 +1,200 @@
+/*
+ * lp.h -- C ABI of the MI355X (gfx950) dense LU solver library (liblp.so).
+ *
+ * The library solves dense systems A X = B the way the LINPACK benchmark
+ * defines them (paper, section "High Performance Linpack"): A is decomposed
+ * into a lower and an upper factor, then L Y = B and U X = Y are solved, and
+ * the result is checked with a scaled residual.  The factorization is the
+ * blocked right-looking scheme of the paper's "Base Implementation" (figure
+ * fig:lu_iteration): per block column, factor the diagonal/panel block,
+ * update the blocks to its right with L ("top" blocks), and update the inner
+ * blocks with one matrix multiplication; the next block column is factored
+ * while the rest of the multiplication still runs (the overlap of the
+ * communication and update phases, figure fig:lu_execution_schedule_pcie).
+ * Unlike the paper's FPGA design the factorization pivots (partial pivoting);
+ * on diagonally dominant input (the HPL-AI rule the paper adopts) the pivot
+ * search keeps every diagonal row, so the result is the paper's.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrix pointers are DEVICE pointers (hipMalloc or torch.empty(...,
+ *     device='cuda') memory) unless stated otherwise.  Matrices are row-major:
+ *     element (i, j) lives at M[i * ld + j], with the leading dimension ld >= the
+ *     number of columns (ld >= 1).
+ *   - ipiv is 0-based int32 with sequential-swap meaning: at step j, row j was
+ *     exchanged with row ipiv[j] >= j.  Pivot choice: the lowest row index
+ *     among the largest |a_ij| (a NaN is never chosen unless it sits on the
+ *     diagonal).
+ *   - The caller owns every buffer, including workspaces; the library allocates
+ *     no device memory on these paths (the serving API is the exception and
+ *     says so).
+ *   - Work is stream-ordered on `stream` (a hipStream_t passed as void*; NULL =
+ *     the default stream) and calls return without waiting for the device,
+ *     except lu_solve_ir, which must read residuals on the host.
+ *   - Return value (synchronous): LP_OK (0); -i when the i-th argument is
+ *     illegal (LAPACK style, 1-based); LP_ENOSPC when a workspace is too small;
+ *     LP_ENOTSUP for a size/precision combination the kernels do not cover;
+ *     LP_EHIP_BASE - e for a HIP runtime error e.  lp_strerror() names them.
+ *   - Numerical status is asynchronous, in device memory: *info = 0, or k + 1
+ *     for the first exact zero pivot in column k (LAPACK getrf meaning; the
+ *     column is then left unscaled and the factorization continues), or
+ *     LP_INFO_BARRIER_TIMEOUT if an internal grid barrier gave up waiting
+ *     (results are then invalid; this never happens on a healthy device).
+ */
+#ifndef LP_H_
+#define LP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LP_OK 0
+#define LP_ENOSPC (-900)
+#define LP_ENOTSUP (-901)
+#define LP_EHIP_BASE (-1000)
+#define LP_INFO_BARRIER_TIMEOUT (-77)
+
+/* Precision of the trailing-matrix update operands.  LP_FP64: everything in
+ * binary64 (FP64 MFMA).  LP_FP32: binary32 storage, panel and operands.
+ * LP_BF16 / LP_FP16: binary32 storage, panel and triangular solves, but the
+ * operands of the inner-block multiplication are rounded to bfloat16 / half
+ * (round to nearest even) and accumulated in binary32 on MFMA. */
+typedef enum { LP_FP64 = 0, LP_FP32 = 1, LP_BF16 = 2, LP_FP16 = 3 } lp_prec;
+
+/* Text for a return code. Never NULL. */
+const char *lp_strerror(int code);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int lp_version(void);
+
+/* ---------------------------------------------------------------- factor */
+
+/* Bytes of device workspace lu_factor needs for (n, nb, prec).  Host-only,
+ * pure function; returns 0 for invalid arguments. */
+size_t lu_workspace_bytes(int n, int nb, int prec);
+
+/* In-place LU factorization with partial pivoting, P A = L U (paper, section
+ * "High Performance Linpack", blocked right-looking variant of the "Base
+ * Implementation").
+ *   n     order of A (n >= 0; n <= 131072)
+ *   nb    block (panel) width, 1 <= nb <= 1024; the inner multiplication has
+ *         depth nb.  n need not be a multiple of nb.
+ *   prec  lp_prec: LP_FP64 expects A as double; the others expect A as float.
+ *   A     device, n x n row-major, ld lda >= max(1, n); overwritten by L (unit
+ *         lower, diagonal not stored) and U.
+ *   ipiv  device int32[n]; info device int32[1].
+ *   work  device workspace of at least lu_workspace_bytes(n, nb, prec) bytes,
+ *         8-byte aligned; its contents on entry do not matter.
+ *   stream hipStream_t or NULL.
+ * The call may create one internal stream and a few events for the
+ * look-ahead and joins it back into `stream` before returning. */
+int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
+              void *work, size_t work_bytes, void *stream);
+
+/* ----------------------------------------------------------------- solve */
+
+/* Solve A X = B with the factors from lu_factor: apply the interchanges to B,
+ * then L Y = P B (unit lower) and U X = Y (paper: L y = b, then U x = y).
+ *   storage  LP_FP64 (LU and B double) or LP_FP32 (LU and B float).
+ *   LU, lda, ipiv, info  as written by lu_factor (device).
+ *   B     device, n x nrhs row-major, ld ldb >= max(1, nrhs); overwritten by X.
+ *   solve_status device int32[1] (may be NULL): set to 0 on success; set to 1
+ *         and B left unchanged when *info != 0.
+ * Requires no workspace. */
+int lu_solve(int n, int storage, const void *LU, int lda, const int32_t *ipiv,
+             const int32_t *info, void *B, int ldb, int nrhs, int32_t *solve_status,
+             void *stream);
+
+/* -------------------------------------------------------------- residual */
+
+/* The benchmark's residual check in binary64 on the ORIGINAL A and B:
+ *   s_c = ||A x_c - b_c||_inf / (eps * (||A||_inf ||x_c||_inf + ||b_c||_inf) * n),
+ * eps = 2^-53, per right-hand side c (pass if s_c < 16).  The paper prints a
+ * garbled normalised residual; this is the standard HPL form.
+ *   A (n x n, lda), X (n x nrhs, ldx), B (n x nrhs, ldb): device, double.
+ *   out   device double[5 * nrhs]: {s, ||r||_inf, ||A||_inf, ||x||_inf,
+ *         ||b||_inf} per right-hand side.  A NaN input yields NaN s (fails).
+ * Deterministic: the same inputs give bitwise the same out. */
+int residual_check(int n, const double *A, int lda, const double *X, int ldx,
+                   const double *B, int ldb, int nrhs, double *out, void *stream);
+
+/* ------------------------------------------------ mixed precision + IR */
+
+typedef struct {
+  int iterations;        /* refinement steps taken (corrections applied)    */
+  int converged;         /* 1 if the final scaled residual is < 16          */
+  int fell_back;         /* 1 if the FP64 factorization had to be used      */
+  int info;              /* info of the low-precision factorization        */
+  int fallback_info;     /* info of the FP64 fallback (if it ran)           */
+  int history_len;       /* entries used in history                         */
+  double scaled_residual;/* final max_c s_c                                 */
+  double history[64];    /* max_c s_c after x0 and after each correction    */
+  double t_convert_ms, t_factor_ms, t_solve0_ms, t_refine_ms, t_fallback_ms, t_total_ms;
+} lp_ir_report;
+
+/* Bytes of device workspace lu_solve_ir needs. */
+size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs);
+
+/* Mixed-precision solve with iterative refinement.  The matrix is copied to
+ * binary32, factored with the inner update in `prec` (LP_FP32, LP_BF16 or
+ * LP_FP16), and x0 solved from those factors; then, repeatedly,
+ * r = B - A x (binary64, original A), d = solve(low-precision factors, r),
+ * x += d (binary64) until max_c s_c < 16.  Refinement stops as failed after
+ * max_iter corrections, when the residual is not finite, or when it grows two
+ * steps in a row; the matrix is then factored in binary64 (workspace reused)
+ * and solved directly (fell_back = 1).
+ *   A (n x n, lda), B (n x nrhs, ldb): device double, unchanged.
+ *   X: device double n x nrhs (ldx), output.
+ *   rep: HOST pointer, filled on return.  This call synchronizes `stream`
+ *   once per refinement step to read the residual. */
+int lu_solve_ir(int n, int nb, int prec, const double *A, int lda, const double *B,
+                int ldb, double *X, int ldx, int nrhs, int max_iter, void *work,
+                size_t work_bytes, lp_ir_report *rep, void *stream);
+
+/* --------------------------------------------- building blocks (exported) */
+/* The steps of one block column, callable on their own (used by the tests
+ * and by callers that schedule the steps themselves).  Same conventions. */
+
+/* Panel factorization: partial-pivoting LU of the m x w column panel at
+ * A (rows 0..m-1, columns 0..w-1 of a row-major array with ld lda), w <= m.
+ * ipiv[0..w-1] receive panel-relative pivot rows; *info as lu_factor
+ * (panel-relative column).  The interchanges are applied to the w panel
+ * columns only.  work: lu_workspace_bytes(m, w, prec) bytes.  prec selects
+ * double (LP_FP64) or float (others). */
+int lp_panel_factor(int m, int w, int prec, void *A, int lda, int32_t *ipiv,
+                    int32_t *info, void *work, size_t work_bytes, void *stream);
+
+/* Row interchanges: for j = k1 .. k2-1 in order, swap rows j and ipiv[j]
+ * (absolute row indices, ipiv[j] >= j) over columns [c0, c1) of A (double if
+ * prec == LP_FP64 else float).  work: lp_laswp_workspace_bytes(k2 - k1). */
+size_t lp_laswp_workspace_bytes(int nswaps);
+int lp_laswp(int prec, void *A, int lda, int c0, int c1, int k1, int k2,
+             const int32_t *ipiv, void *work, size_t work_bytes, void *stream);
+
+/* Triangular solve with a unit lower triangular L (m x m, ld ldl):
+ * B := L^-1 B for B m x ncols (ld ldb), in place.  Column-independent.  The
+ * blocks to the right of the panel in the paper's "top blocks" update. */
+int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void *B,
+                       int ldb, void *stream);
+
+/* Inner-block update C := C - A B with A M x K (lda), B K x N (ldb), C M x N
+ * (ldc); prec LP_FP64: all double on FP64 MFMA; LP_FP32: float operands on
+ * FP32 MFMA; LP_BF16 / LP_FP16: float A, B, C in memory, operands rounded to
+ * bfloat16 / half (nearest even) on the way into the matrix cores, binary32
+ * accumulation.  The paper's inner-block matrix multiplication. */
+int lp_gemm_update(int prec, int M, int N, int K, const void *A, int lda, const void *B,
+                   int ldb, void *C, int ldc, void *stream);
+
+/* Element-wise copies between binary64 and binary32 (row-major, rows x cols):
+ * to_f32 != 0 converts src double -> dst float (round to nearest even),
+ * else src float -> dst double. */
+int lp_convert(int to_f32, int rows, int cols, const void *src, int lds, void *dst, int ldd,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H_ */

@@ -1,0 +1,263 @@
+"""MI355X (gfx950) dense LU solver: Python binding of liblp.so.
+
+Argument marshalling only: every step of the factorization, the solves and the
+residual check runs in the HIP kernels of ``liblp.so`` (``include/lp.h``).
+PyTorch supplies device memory and the current HIP stream.  Importing this
+package loads the library and raises if it has not been built
+(``python -m paper_2202_13995_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblp.so")
+
+FP64, FP32, BF16, FP16 = 0, 1, 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
+LP_OK = 0
+LP_ENOSPC = -900
+LP_ENOTSUP = -901
+INFO_BARRIER_TIMEOUT = -77
+
+
+class LPError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {code} ({strerror(code)})")
+        self.code = code
+
+
+class IRReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("fell_back", ctypes.c_int), ("info", ctypes.c_int),
+                ("fallback_info", ctypes.c_int), ("history_len", ctypes.c_int),
+                ("scaled_residual", ctypes.c_double), ("history", ctypes.c_double * 64),
+                ("t_convert_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
+                ("t_solve0_ms", ctypes.c_double), ("t_refine_ms", ctypes.c_double),
+                ("t_fallback_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}
+        d["history"] = [self.history[i] for i in range(self.history_len)]
+        return d
+
+
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_SZ = ctypes.c_size_t
+_D = ctypes.c_double
+
+# name -> (restype, argtypes); the order follows include/lp.h
+SIGNATURES = {
+    "lp_strerror": (ctypes.c_char_p, [_I]),
+    "lp_version": (_I, []),
+    "lu_workspace_bytes": (_SZ, [_I, _I, _I]),
+    "lu_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "lu_solve": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP]),
+    "residual_check": (_I, [_I, _VP, _I, _VP, _I, _VP, _I, _I, _VP, _VP]),
+    "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
+    "lu_solve_ir": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ,
+                         ctypes.POINTER(IRReport), _VP]),
+    "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "lp_laswp_workspace_bytes": (_SZ, [_I]),
+    "lp_laswp": (_I, [_I, _VP, _I, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
+    "lp_trsm_lower_unit": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
+    "lp_gemm_update": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
+    "lp_convert": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
+}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2202_13995_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.lp_strerror(int(code)).decode()
+
+
+def _check(fn: str, rc: int) -> None:
+    if rc != LP_OK:
+        raise LPError(fn, rc)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _mat(t: torch.Tensor, dtype=None, name="matrix") -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D row-major with unit column stride")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.stride(0) if t.shape[0] > 0 else max(1, t.shape[1])
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def storage_dtype(prec) -> torch.dtype:
+    return torch.float64 if _prec(prec) == FP64 else torch.float32
+
+
+def workspace(n: int, nb: int, prec="fp64", device="cuda") -> torch.Tensor:
+    nbytes = lib.lu_workspace_bytes(n, nb, _prec(prec))
+    if nbytes == 0:
+        raise ValueError(f"unsupported (n={n}, nb={nb}, prec={prec})")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
+              stream=None):
+    """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device."""
+    p = _prec(prec)
+    lda = _mat(A, storage_dtype(p), "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if work is None:
+        work = workspace(n, nb, p, A.device)
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check("lu_factor", lib.lu_factor(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
+                                      info.data_ptr(), work.data_ptr(), work.numel(),
+                                      _stream(stream)))
+    return ipiv, info
+
+
+def lu_solve(LU: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, B: torch.Tensor,
+             status=None, stream=None):
+    """In place: B := A^-1 B from the factors. Returns the device solve status."""
+    dt = LU.dtype
+    storage = FP64 if dt == torch.float64 else FP32
+    lda = _mat(LU, dt, "LU")
+    ldb = _mat(B, dt, "B")
+    n = LU.shape[0]
+    if B.shape[0] != n:
+        raise ValueError("B has the wrong number of rows")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=LU.device)
+    _check("lu_solve", lib.lu_solve(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
+                                    info.data_ptr(), B.data_ptr(), ldb, B.shape[1],
+                                    status.data_ptr(), _stream(stream)))
+    return status
+
+
+def residual_check(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out=None,
+                   stream=None) -> torch.Tensor:
+    """Device tensor (nrhs, 5): {s, ||r||, ||A||, ||x||, ||b||} per right-hand side."""
+    lda = _mat(A, torch.float64, "A")
+    ldx = _mat(X, torch.float64, "X")
+    ldb = _mat(B, torch.float64, "B")
+    n = A.shape[0]
+    nrhs = X.shape[1]
+    if out is None:
+        out = torch.empty((max(nrhs, 1), 5), dtype=torch.float64, device=A.device)
+    _check("residual_check", lib.residual_check(n, A.data_ptr(), lda, X.data_ptr(), ldx,
+                                                B.data_ptr(), ldb, nrhs, out.data_ptr(),
+                                                _stream(stream)))
+    return out
+
+
+def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: int = 30,
+             X=None, work=None, stream=None):
+    """Mixed-precision solve with binary64 iterative refinement. Returns (X, report)."""
+    p = _prec(prec)
+    lda = _mat(A, torch.float64, "A")
+    ldb = _mat(B, torch.float64, "B")
+    n, nrhs = B.shape
+    if X is None:
+        X = torch.empty_like(B)
+    ldx = _mat(X, torch.float64, "X")
+    if work is None:
+        nbytes = lib.lu_solve_ir_workspace_bytes(n, nb, p, nrhs)
+        if nbytes == 0:
+            raise ValueError("unsupported solve_ir arguments")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    rep = IRReport()
+    _check("lu_solve_ir", lib.lu_solve_ir(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                          X.data_ptr(), ldx, nrhs, max_iter, work.data_ptr(),
+                                          work.numel(), ctypes.byref(rep), _stream(stream)))
+    return X, rep
+
+
+# ------------------------------------------------------------ building blocks
+def panel_factor(P: torch.Tensor, prec="fp64", work=None, stream=None):
+    p = _prec(prec)
+    ld = _mat(P, storage_dtype(p), "panel")
+    m, w = P.shape
+    if work is None:
+        work = workspace(m, max(w, 1), p, P.device)
+    ipiv = torch.empty(max(w, 1), dtype=torch.int32, device=P.device)
+    info = torch.empty(1, dtype=torch.int32, device=P.device)
+    _check("lp_panel_factor", lib.lp_panel_factor(m, w, p, P.data_ptr(), ld, ipiv.data_ptr(),
+                                                  info.data_ptr(), work.data_ptr(),
+                                                  work.numel(), _stream(stream)))
+    return ipiv, info
+
+
+def laswp(A: torch.Tensor, c0: int, c1: int, k1: int, k2: int, ipiv: torch.Tensor,
+          stream=None) -> None:
+    p = FP64 if A.dtype == torch.float64 else FP32
+    lda = _mat(A, None, "A")
+    nbytes = lib.lp_laswp_workspace_bytes(k2 - k1)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=A.device)
+    _check("lp_laswp", lib.lp_laswp(p, A.data_ptr(), lda, c0, c1, k1, k2, ipiv.data_ptr(),
+                                    work.data_ptr(), work.numel(), _stream(stream)))
+
+
+def trsm_lower_unit(L: torch.Tensor, B: torch.Tensor, stream=None) -> None:
+    p = FP64 if B.dtype == torch.float64 else FP32
+    ldl = _mat(L, B.dtype, "L")
+    ldb = _mat(B, B.dtype, "B")
+    _check("lp_trsm_lower_unit", lib.lp_trsm_lower_unit(p, B.shape[0], B.shape[1], L.data_ptr(),
+                                                        ldl, B.data_ptr(), ldb, _stream(stream)))
+
+
+def gemm_update(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=None,
+                stream=None) -> None:
+    """C := C - A B on the matrix cores (prec defaults to the storage precision)."""
+    if prec is None:
+        prec = FP64 if C.dtype == torch.float64 else FP32
+    p = _prec(prec)
+    dt = storage_dtype(p)
+    lda = _mat(A, dt, "A")
+    ldb = _mat(B, dt, "B")
+    ldc = _mat(C, dt, "C")
+    M, K = A.shape
+    N = B.shape[1]
+    if B.shape[0] != K or C.shape != (M, N):
+        raise ValueError("shape mismatch")
+    _check("lp_gemm_update", lib.lp_gemm_update(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                                C.data_ptr(), ldc, _stream(stream)))
+
+
+def convert(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    to_f32 = 1 if src.dtype == torch.float64 else 0
+    lds = _mat(src, None, "src")
+    ldd = _mat(dst, None, "dst")
+    _check("lp_convert", lib.lp_convert(to_f32, src.shape[0], src.shape[1], src.data_ptr(), lds,
+                                        dst.data_ptr(), ldd, _stream(stream)))
+
+
+def flops(n: int, nrhs: int = 1) -> float:
+    """LINPACK operation count of factor + solve: 2/3 n^3 + 2 n^2 per right-hand side."""
+    return 2.0 / 3.0 * n ** 3 + 2.0 * n ** 2 * nrhs

@@ -1,0 +1,71 @@
+// Shared helpers for the gfx950 kernels and the host driver of liblp.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lp.h"
+
+#define LP_HIP_TRY(expr)                              \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return LP_EHIP_BASE - (int)e_; \
+  } while (0)
+
+#define LP_LAUNCH_CHECK()                                  \
+  do {                                                     \
+    hipError_t e_ = hipGetLastError();                     \
+    if (e_ != hipSuccess) return LP_EHIP_BASE - (int)e_;   \
+  } while (0)
+
+namespace lp {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+__host__ __device__ inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+// Number of compute units of the current device (cached per device id).
+int num_cus();
+
+// ---------------------------------------------------------------- kernels
+// All launchers return LP_OK or LP_EHIP_BASE - hipError.  Arguments are
+// assumed valid (checked by the C ABI layer).
+
+// C := C - A B (row-major, prec as lp_prec).
+int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long lda,
+                       const void* B, long long ldb, void* C, long long ldc, hipStream_t s);
+
+// B := L^-1 B, L unit lower m x m.
+template <typename T>
+int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
+                           hipStream_t s);
+
+// Swap plan for interchanges k1..k2-1 (device ipiv, absolute rows): writes a
+// gather list (dst, src) into plan; see panel.hip.
+size_t swap_plan_bytes(int nswaps);
+int launch_swap_plan(const int32_t* ipiv, int k1, int k2, void* plan, hipStream_t s);
+// Apply a plan to columns [c0, c1) and [c2, c3) of A.
+template <typename T>
+int launch_swap_apply(T* A, long long lda, int c0, int c1, int c2, int c3, int nswaps,
+                      const void* plan, hipStream_t s);
+
+// Panel leaf: factor columns [j0, j0+w) over rows [j0, m) of A (absolute
+// indices), w <= kLeafMax.  ipiv/info absolute.  barrier: zeroed int slot.
+constexpr int kLeafMax = 32;
+size_t leaf_slots_bytes(int m, int w);
+template <typename T>
+int launch_panel_leaf(int m, int j0, int w, T* A, long long lda, int32_t* ipiv, int32_t* info,
+                      int info_base, void* slots, unsigned* barrier, hipStream_t s);
+
+// Zero a range of 32-bit words (a kernel, not a memset node).
+int launch_zero_words(void* p, size_t nwords, hipStream_t s);
+
+// Element-wise precision conversion.
+int launch_convert(int to_f32, int rows, int cols, const void* src, long long lds, void* dst,
+                   long long ldd, hipStream_t s);
+
+}  // namespace lp

@@ -1,0 +1,512 @@
+// Panel-side kernels of the blocked LU: the pivoted panel leaf, the row
+// interchanges, and the unit-lower triangular solve.
+//
+// Paper, section "High Performance Linpack", "Base Implementation": each
+// iteration factors the diagonal block into L and U, updates the blocks to its
+// right with L (the "top" blocks, a triangular solve here) and the blocks
+// below it with U (the "left" blocks).  With partial pivoting the left blocks
+// are factored together with the diagonal block as one tall column panel,
+// and every chosen pivot row is exchanged with the diagonal row across the
+// whole matrix.
+#include <climits>
+
+#include "common.h"
+#include "swap_plan.h"
+
+namespace lp {
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void zero_words_kernel(uint32_t* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+int launch_zero_words(void* p, size_t nwords, hipStream_t s) {
+  if (nwords == 0) return LP_OK;
+  size_t blocks = (nwords + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p,
+                     nwords);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(int rows, int cols, const S* __restrict__ src, long long lds,
+                               D* __restrict__ dst, long long ldd) {
+  const long long total = (long long)rows * cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / cols;
+    const long long c = e - r * cols;
+    dst[r * ldd + c] = (D)src[r * lds + c];
+  }
+}
+
+int launch_convert(int to_f32, int rows, int cols, const void* src, long long lds, void* dst,
+                   long long ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return LP_OK;
+  long long blocks = ((long long)rows * cols + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (to_f32)
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       rows, cols, (const double*)src, lds, (float*)dst, ldd);
+  else
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       rows, cols, (const float*)src, lds, (double*)dst, ldd);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+// --------------------------------------------------------- grid barrier
+// All workgroups of a launch meet here.  Every workgroup is resident at once
+// (the launcher keeps the grid at most one workgroup per compute unit, and no
+// other kernel depends on this one), so the wait ends; it is still bounded by
+// the device's constant 100 MHz clock so that a stuck launch drains instead of
+// hanging.  Returns false on timeout.
+constexpr unsigned long long kBarrierTimeoutTicks = 2000000000ull;  // 20 s at 100 MHz
+
+__device__ bool grid_barrier(unsigned* ctr, unsigned target, int* s_flag) {
+  // make this thread's global writes visible device-wide before arriving
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int ok = 1;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
+        ok = 0;
+        break;
+      }
+    }
+    *s_flag = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *s_flag != 0;
+}
+
+// ------------------------------------------------------------- panel leaf
+// Factors columns [j0, j0 + w) of rows [j0, m) with partial pivoting, w <= 32.
+// Workgroup g owns rows [j0 + g R, j0 + (g + 1) R) and keeps their w entries in
+// LDS (column-major, R rows per column).  Per column:
+//   1. each workgroup finds its candidate: the largest |a| among its active
+//      rows (a NaN counts as smaller than every number), lowest row on ties;
+//      it publishes the candidate's key, row index and w values, and the owner
+//      of the diagonal row publishes that row;
+//   2. grid barrier;
+//   3. every workgroup reduces the G candidates the same way (so the winner is
+//      the lowest-index maximum), keeps the diagonal row if its entry is NaN
+//      (a strict '>' scan never leaves a NaN start), exchanges the two rows in
+//      its LDS if it owns them, then scales its rows below the diagonal by the
+//      pivot (a division) and applies the rank-1 update to the remaining
+//      columns of the leaf.
+// Slots are double-buffered by column parity: a workgroup can only overwrite a
+// buffer after every workgroup has passed the next barrier.
+
+struct LeafLayout {
+  size_t key_off, idx_off, rows_off, diag_off, flag_off, buf_bytes;
+};
+
+template <typename T>
+__host__ __device__ inline LeafLayout leaf_layout(int G) {
+  LeafLayout L;
+  size_t off = 0;
+  L.key_off = off;
+  off += sizeof(double) * (size_t)G;
+  L.idx_off = off;
+  off += sizeof(int) * (size_t)G;
+  off = (off + 15) & ~(size_t)15;
+  L.rows_off = off;
+  off += sizeof(T) * (size_t)G * kLeafMax;
+  L.diag_off = off;
+  off += sizeof(T) * kLeafMax;
+  L.flag_off = off;
+  off += 16;
+  off = (off + 255) & ~(size_t)255;
+  L.buf_bytes = off;
+  return L;
+}
+
+size_t leaf_slots_bytes(int m, int w) {
+  (void)m;
+  (void)w;
+  // G <= 1024 workgroups, double-sized entries (covers float too)
+  return 2 * leaf_layout<double>(1024).buf_bytes;
+}
+
+__device__ __forceinline__ bool better(double ka, int ia, double kb, int ib) {
+  // is (ka, ia) a better pivot candidate than (kb, ib)?
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void panel_leaf_kernel(int m, int j0, int w,
+                                                         T* __restrict__ A, long long lda,
+                                                         int32_t* __restrict__ ipiv,
+                                                         int32_t* __restrict__ info, int R,
+                                                         int G, char* __restrict__ slots,
+                                                         unsigned* __restrict__ barrier) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);  // [w][R]
+  __shared__ double red_key[4];
+  __shared__ int red_idx[4];
+  __shared__ T prow[kLeafMax];
+  __shared__ T drow[kLeafMax];
+  __shared__ int s_p;
+  __shared__ int s_flag;
+
+  const LeafLayout lay = leaf_layout<T>(G);
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int base = j0 + g * R;
+  const int nrows = min(R, m - base);
+
+  for (int e = tid; e < nrows * w; e += blockDim.x) {
+    const int r = e / w;
+    const int c = e - r * w;
+    tile[c * R + r] = A[(long long)(base + r) * lda + j0 + c];
+  }
+  __syncthreads();
+
+  for (int jj = 0; jj < w; ++jj) {
+    const int dg = j0 + jj;  // diagonal row (global)
+    char* sb = slots + (size_t)(jj & 1) * lay.buf_bytes;
+    double* skey = reinterpret_cast<double*>(sb + lay.key_off);
+    int* sidx = reinterpret_cast<int*>(sb + lay.idx_off);
+    T* srows = reinterpret_cast<T*>(sb + lay.rows_off);
+    T* sdiag = reinterpret_cast<T*>(sb + lay.diag_off);
+    int* sflag = reinterpret_cast<int*>(sb + lay.flag_off);
+
+    // 1. local candidate
+    double bk = -2.0;
+    int bi = INT_MAX;
+    for (int r = tid; r < nrows; r += blockDim.x) {
+      const int gi = base + r;
+      if (gi >= dg) {
+        const T v = tile[jj * R + r];
+        const double k = (v != v) ? -1.0 : fabs((double)v);
+        if (better(k, gi, bk, bi)) {
+          bk = k;
+          bi = gi;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ok = __shfl_xor(bk, off);
+      const int oi = __shfl_xor(bi, off);
+      if (better(ok, oi, bk, bi)) {
+        bk = ok;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      red_key[tid >> 6] = bk;
+      red_idx[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int t = 1; t < 4; ++t)
+        if (better(red_key[t], red_idx[t], bk, bi)) {
+          bk = red_key[t];
+          bi = red_idx[t];
+        }
+      s_p = bi;
+    }
+    __syncthreads();
+    const int cand = s_p;
+    __syncthreads();
+    if (G > 1) {
+      if (tid == 0) {
+        double kk = -2.0;
+        if (cand != INT_MAX) {
+          const T v = tile[jj * R + (cand - base)];
+          kk = (v != v) ? -1.0 : fabs((double)v);
+        }
+        skey[g] = kk;
+        sidx[g] = cand;
+      }
+      if (tid < w) srows[(size_t)g * kLeafMax + tid] = (cand != INT_MAX) ? tile[tid * R + (cand - base)] : T(0);
+      if (dg >= base && dg < base + nrows) {
+        if (tid < w) sdiag[tid] = tile[tid * R + (dg - base)];
+        if (tid == 0) {
+          const T dv = tile[jj * R + (dg - base)];
+          *sflag = (dv != dv) ? 1 : 0;
+        }
+      }
+      // 2. everyone meets
+      if (!grid_barrier(barrier, (unsigned)G * (unsigned)(jj + 1), &s_flag)) {
+        if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
+        return;
+      }
+      // 3. global winner
+      double k2 = -3.0;
+      int i2 = INT_MAX;
+      if (tid < G) {
+        k2 = skey[tid];
+        i2 = sidx[tid];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ok = __shfl_xor(k2, off);
+        const int oi = __shfl_xor(i2, off);
+        if (better(ok, oi, k2, i2)) {
+          k2 = ok;
+          i2 = oi;
+        }
+      }
+      if ((tid & 63) == 0) {
+        red_key[tid >> 6] = k2;
+        red_idx[tid >> 6] = i2;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int t = 1; t < 4; ++t)
+          if (better(red_key[t], red_idx[t], k2, i2)) {
+            k2 = red_key[t];
+            i2 = red_idx[t];
+          }
+        s_p = (*sflag) ? dg : i2;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (tid < w) {
+        const T dv = sdiag[tid];
+        drow[tid] = dv;
+        prow[tid] = (p == dg) ? dv : srows[(size_t)((p - j0) / R) * kLeafMax + tid];
+      }
+    } else {
+      // single workgroup: everything is local
+      if (tid == 0) {
+        const T dv = tile[jj * R + (dg - base)];
+        s_p = (dv != dv) ? dg : cand;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (tid < w) {
+        drow[tid] = tile[tid * R + (dg - base)];
+        prow[tid] = tile[tid * R + (p - base)];
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    const T piv = prow[jj];
+    if (g == 0 && tid == 0) {
+      ipiv[dg] = p;
+      if (piv == T(0) && *info == 0) *info = dg + 1;
+    }
+    // exchange rows dg and p inside this workgroup's LDS
+    if (p != dg && tid < w) {
+      if (p >= base && p < base + nrows) tile[tid * R + (p - base)] = drow[tid];
+      if (dg >= base && dg < base + nrows) tile[tid * R + (dg - base)] = prow[tid];
+    }
+    __syncthreads();
+    if (piv != T(0)) {
+      for (int r = tid; r < nrows; r += blockDim.x) {
+        if (base + r > dg) {
+          const T l = tile[jj * R + r] / piv;
+          tile[jj * R + r] = l;
+          for (int c = jj + 1; c < w; ++c) tile[c * R + r] -= l * prow[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int e = tid; e < nrows * w; e += blockDim.x) {
+    const int r = e / w;
+    const int c = e - r * w;
+    A[(long long)(base + r) * lda + j0 + c] = tile[c * R + r];
+  }
+}
+
+template <typename T>
+int launch_panel_leaf(int m, int j0, int w, T* A, long long lda, int32_t* ipiv, int32_t* info,
+                      int info_base, void* slots, unsigned* barrier, hipStream_t s) {
+  (void)info_base;
+  const int rows = m - j0;
+  if (rows <= 0 || w <= 0) return LP_OK;
+  if (w > kLeafMax) return LP_ENOTSUP;
+  const int ncu = num_cus();
+  int R = (int)cdiv(rows, ncu);
+  R = (int)(cdiv(R, 64) * 64);
+  if (R < 256) R = 256;
+  const int G = (int)cdiv(rows, R);
+  const size_t lds = sizeof(T) * (size_t)R * w;
+  if (lds > 160 * 1024 - 2048) return LP_ENOTSUP;
+  if (G > ncu || G > 256) return LP_ENOTSUP;
+  hipLaunchKernelGGL((panel_leaf_kernel<T>), dim3(G), dim3(256), lds, s, m, j0, w, A, lda, ipiv,
+                     info, R, G, (char*)slots, barrier);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template int launch_panel_leaf<double>(int, int, int, double*, long long, int32_t*, int32_t*,
+                                       int, void*, unsigned*, hipStream_t);
+template int launch_panel_leaf<float>(int, int, int, float*, long long, int32_t*, int32_t*, int,
+                                      void*, unsigned*, hipStream_t);
+
+// ------------------------------------------------------- row interchanges
+// The interchanges of steps k1..k2-1 (row j <-> row ipiv[j] >= j, in order)
+// form one permutation of at most 2 (k2 - k1) rows.  Writing T for the rows
+// k1..k2-1 and B[t] for the original row whose contents sit in row k1 + t just
+// before step t:
+//   B[t] = B[h] if h, the last earlier step whose pivot row was k1 + t, exists,
+//          else k1 + t;
+//   the final contents of row k1 + t come from B[pred] (pred = last earlier
+//   step with the same pivot row) or from the pivot row itself if it was never
+//   a pivot before (or B[t] when the step keeps its own row);
+//   a row outside T ends with B[t] of the last step that chose it.
+// B follows chains that only point backwards, resolved by pointer jumping, so
+// the whole plan is built in parallel with O(k) work per thread; the
+// exchange itself is then a gather: every (dst, src) pair reads before any
+// write.  Contents of the plan: nent, then dst[], src[] (compacted).
+constexpr int kPlanMax = 1024;                 // swaps per plan
+constexpr int kPlanDst = 4;                    // int offsets inside a plan
+constexpr int kPlanSrc = 4 + 2 * kPlanMax;
+constexpr int kPlanInts = 4 + 4 * kPlanMax;
+
+size_t swap_plan_bytes(int nswaps) {
+  (void)nswaps;
+  return sizeof(int) * (size_t)kPlanInts;
+}
+
+__global__ __launch_bounds__(1024) void swap_plan_kernel(const int32_t* __restrict__ ipiv,
+                                                         int k1, int k2, int* __restrict__ plan) {
+  __shared__ int piv[kPlanMax];
+  __shared__ int nxt[kPlanMax];
+  __shared__ int Bv[kPlanMax];
+  __shared__ int flag[2 * kPlanMax];
+  const int k = k2 - k1;
+  if ((int)threadIdx.x < k) piv[threadIdx.x] = ipiv[k1 + threadIdx.x];
+  __syncthreads();
+  build_swap_plan(piv, k1, k2, nxt, Bv, nullptr, flag, plan + kPlanDst, plan + kPlanSrc, plan);
+}
+
+int launch_swap_plan(const int32_t* ipiv, int k1, int k2, void* plan, hipStream_t s) {
+  const int k = k2 - k1;
+  if (k <= 0) return launch_zero_words(plan, 1, s);
+  if (k > kPlanMax) return LP_ENOTSUP;
+  hipLaunchKernelGGL(swap_plan_kernel, dim3(1), dim3(1024), 0, s, ipiv, k1, k2, (int*)plan);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(1024) void swap_apply_kernel(T* __restrict__ A, long long lda,
+                                                          int c0, int c1, int c2, int c3, int CW,
+                                                          const int* __restrict__ plan) {
+  const int nent = plan[0];
+  const int* dst = plan + kPlanDst;
+  const int* src = plan + kPlanSrc;
+  const int chunks1 = (c1 - c0 + CW - 1) / CW;
+  int cs, ce;
+  if ((int)blockIdx.x < chunks1) {
+    cs = c0 + blockIdx.x * CW;
+    ce = min(c1, cs + CW);
+  } else {
+    cs = c2 + (blockIdx.x - chunks1) * CW;
+    ce = min(c3, cs + CW);
+  }
+  const int width = ce - cs;
+  T v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 1024 * q;
+    const int ent = e / CW;
+    const int col = e - ent * CW;
+    if (ent < nent && col < width) v[q] = A[(long long)src[ent] * lda + cs + col];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 1024 * q;
+    const int ent = e / CW;
+    const int col = e - ent * CW;
+    if (ent < nent && col < width) A[(long long)dst[ent] * lda + cs + col] = v[q];
+  }
+}
+
+template <typename T>
+int launch_swap_apply(T* A, long long lda, int c0, int c1, int c2, int c3, int nswaps,
+                      const void* plan, hipStream_t s) {
+  constexpr int Q = 16;
+  if (c1 < c0) c1 = c0;
+  if (c3 < c2) c3 = c2;
+  if (nswaps <= 0 || (c1 == c0 && c3 == c2)) return LP_OK;
+  const int maxent = 2 * nswaps;
+  int CW = 64;
+  while (CW > 1 && maxent * CW > 1024 * Q) CW >>= 1;
+  const long long blocks = cdiv(c1 - c0, CW) + cdiv(c3 - c2, CW);
+  hipLaunchKernelGGL((swap_apply_kernel<T, Q>), dim3((unsigned)blocks), dim3(1024), 0, s, A, lda,
+                     c0, c1, c2, c3, CW, (const int*)plan);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template int launch_swap_apply<double>(double*, long long, int, int, int, int, int, const void*,
+                                       hipStream_t);
+template int launch_swap_apply<float>(float*, long long, int, int, int, int, int, const void*,
+                                      hipStream_t);
+
+// ------------------------------------------------ unit lower triangular solve
+// B := L^-1 B, L unit lower m x m: the paper's "top blocks" update of the
+// blocks right of the diagonal block with its lower factor.  Columns of B are
+// independent; each thread owns one column and runs forward substitution over
+// blocks of 16 rows held in registers (left-looking: the rows already solved
+// are re-read from its own column, the L entries are uniform across the wave).
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_lower_unit_kernel(int m, int ncols,
+                                                              const T* __restrict__ L,
+                                                              long long ldl, T* __restrict__ B,
+                                                              long long ldb) {
+  constexpr int RB = 16;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = c < ncols;
+  for (int rb = 0; rb < m; rb += RB) {
+    const int nr = min(RB, m - rb);
+    T x[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) x[r] = (ok && r < nr) ? B[(long long)(rb + r) * ldb + c] : T(0);
+    for (int k = 0; k < rb; ++k) {
+      const T xk = ok ? B[(long long)k * ldb + c] : T(0);
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) x[r] -= L[(long long)(rb + r) * ldl + k] * xk;
+    }
+#pragma unroll
+    for (int r = 1; r < RB; ++r) {
+      if (r < nr) {
+#pragma unroll
+        for (int q = 0; q < r; ++q) x[r] -= L[(long long)(rb + r) * ldl + rb + q] * x[q];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (ok && r < nr) B[(long long)(rb + r) * ldb + c] = x[r];
+  }
+}
+
+template <typename T>
+int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
+                           hipStream_t s) {
+  if (m <= 0 || ncols <= 0) return LP_OK;
+  const int threads = 256;
+  const long long blocks = cdiv(ncols, threads);
+  hipLaunchKernelGGL((trsm_lower_unit_kernel<T>), dim3((unsigned)blocks), dim3(threads), 0, s, m,
+                     ncols, L, ldl, B, ldb);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template int launch_trsm_lower_unit<double>(int, int, const double*, long long, double*,
+                                            long long, hipStream_t);
+template int launch_trsm_lower_unit<float>(int, int, const float*, long long, float*, long long,
+                                           hipStream_t);
+
+}  // namespace lp

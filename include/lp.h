@@ -93,6 +93,32 @@ size_t lu_workspace_bytes(int n, int nb, int prec);
 int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
               void *work, size_t work_bytes, void *stream);
 
+/* Options and per-phase profile for lu_factor_ex. */
+typedef struct {
+  int lookahead; /* 1 (default): factor the next panel on a second stream while the
+                    rest of the inner-block update runs; 0: strictly in order */
+} lp_factor_opts;
+
+typedef struct {
+  int gemm_launches;    /* trailing-update launches                              */
+  int panel_launches;   /* panel factorizations                                  */
+  double gemm_ms;       /* summed device time of the trailing-update launches    */
+  double gemm_flops;    /* their algorithmic flops, 2 M N K per launch           */
+  double gemm_bytes;    /* their algorithmic bytes: C read + write and operands  */
+  double panel_ms;      /* summed device time of the panel factorizations        */
+  double swap_ms;       /* summed device time of the trailing row exchanges      */
+  double swap_bytes;    /* their algorithmic bytes (read + write of moved rows)  */
+  double trsm_ms;       /* summed device time of the triangular solves           */
+  double trsm_flops;    /* their algorithmic flops                               */
+} lp_factor_profile;
+
+/* lu_factor with options (NULL = defaults) and an optional host profile.  When
+ * prof != NULL, HIP events bracket every launch group on the stream that runs
+ * it and the call synchronizes `stream` before filling *prof. */
+int lu_factor_ex(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
+                 void *work, size_t work_bytes, const lp_factor_opts *opts,
+                 lp_factor_profile *prof, void *stream);
+
 /* ----------------------------------------------------------------- solve */
 
 /* Solve A X = B with the factors from lu_factor: apply the interchanges to B,
@@ -175,9 +201,12 @@ int lp_laswp(int prec, void *A, int lda, int c0, int c1, int k1, int k2,
 
 /* Triangular solve with a unit lower triangular L (m x m, ld ldl):
  * B := L^-1 B for B m x ncols (ld ldb), in place.  Column-independent.  The
- * blocks to the right of the panel in the paper's "top blocks" update. */
-int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void *B,
-                       int ldb, void *stream);
+ * blocks to the right of the panel in the paper's "top blocks" update.  work:
+ * device scratch of lp_trsm_workspace_bytes(m) bytes (inverses of the 16 x 16
+ * diagonal blocks). */
+size_t lp_trsm_workspace_bytes(int m);
+int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void *B, int ldb,
+                       void *work, size_t work_bytes, void *stream);
 
 /* Inner-block update C := C - A B with A M x K (lda), B K x N (ldb), C M x N
  * (ldc); prec LP_FP64: all double on FP64 MFMA; LP_FP32: float operands on

@@ -45,6 +45,21 @@ class IRReport(ctypes.Structure):
         return d
 
 
+class FactorOpts(ctypes.Structure):
+    _fields_ = [("lookahead", ctypes.c_int)]
+
+
+class FactorProfile(ctypes.Structure):
+    _fields_ = [("gemm_launches", ctypes.c_int), ("panel_launches", ctypes.c_int),
+                ("gemm_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
+                ("gemm_bytes", ctypes.c_double), ("panel_ms", ctypes.c_double),
+                ("swap_ms", ctypes.c_double), ("swap_bytes", ctypes.c_double),
+                ("trsm_ms", ctypes.c_double), ("trsm_flops", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _VP = ctypes.c_void_p
 _I = ctypes.c_int
 _SZ = ctypes.c_size_t
@@ -56,6 +71,8 @@ SIGNATURES = {
     "lp_version": (_I, []),
     "lu_workspace_bytes": (_SZ, [_I, _I, _I]),
     "lu_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "lu_factor_ex": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, ctypes.POINTER(FactorOpts),
+                          ctypes.POINTER(FactorProfile), _VP]),
     "lu_solve": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP]),
     "residual_check": (_I, [_I, _VP, _I, _VP, _I, _VP, _I, _I, _VP, _VP]),
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
@@ -64,7 +81,8 @@ SIGNATURES = {
     "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lp_laswp_workspace_bytes": (_SZ, [_I]),
     "lp_laswp": (_I, [_I, _VP, _I, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
-    "lp_trsm_lower_unit": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
+    "lp_trsm_workspace_bytes": (_SZ, [_I]),
+    "lp_trsm_lower_unit": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
     "lp_gemm_update": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
     "lp_convert": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
 }
@@ -81,11 +99,25 @@ def _load() -> ctypes.CDLL:
     return lib
 
 
-lib = _load()
+_LIB = None
+
+
+def _lib() -> ctypes.CDLL:
+    """The loaded liblp.so (raises if it is not built; there is no fallback)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+def __getattr__(name):
+    if name == "lib":
+        return _lib()
+    raise AttributeError(name)
 
 
 def strerror(code: int) -> str:
-    return lib.lp_strerror(int(code)).decode()
+    return _lib().lp_strerror(int(code)).decode()
 
 
 def _check(fn: str, rc: int) -> None:
@@ -117,15 +149,16 @@ def storage_dtype(prec) -> torch.dtype:
 
 
 def workspace(n: int, nb: int, prec="fp64", device="cuda") -> torch.Tensor:
-    nbytes = lib.lu_workspace_bytes(n, nb, _prec(prec))
+    nbytes = _lib().lu_workspace_bytes(n, nb, _prec(prec))
     if nbytes == 0:
         raise ValueError(f"unsupported (n={n}, nb={nb}, prec={prec})")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
-              stream=None):
-    """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device."""
+              stream=None, lookahead: bool = True, profile: bool = False):
+    """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device, plus a
+    per-phase profile dict when profile=True (the call then synchronizes)."""
     p = _prec(prec)
     lda = _mat(A, storage_dtype(p), "A")
     n = A.shape[0]
@@ -137,9 +170,15 @@ def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=
         ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
-    _check("lu_factor", lib.lu_factor(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
-                                      info.data_ptr(), work.data_ptr(), work.numel(),
-                                      _stream(stream)))
+    opts = FactorOpts(1 if lookahead else 0)
+    prof = FactorProfile() if profile else None
+    _check("lu_factor", _lib().lu_factor_ex(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
+                                         info.data_ptr(), work.data_ptr(), work.numel(),
+                                         ctypes.byref(opts),
+                                         ctypes.byref(prof) if prof is not None else None,
+                                         _stream(stream)))
+    if profile:
+        return ipiv, info, prof.as_dict()
     return ipiv, info
 
 
@@ -155,7 +194,7 @@ def lu_solve(LU: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, B: torch.
         raise ValueError("B has the wrong number of rows")
     if status is None:
         status = torch.empty(1, dtype=torch.int32, device=LU.device)
-    _check("lu_solve", lib.lu_solve(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
+    _check("lu_solve", _lib().lu_solve(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
                                     info.data_ptr(), B.data_ptr(), ldb, B.shape[1],
                                     status.data_ptr(), _stream(stream)))
     return status
@@ -171,7 +210,7 @@ def residual_check(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out=None,
     nrhs = X.shape[1]
     if out is None:
         out = torch.empty((max(nrhs, 1), 5), dtype=torch.float64, device=A.device)
-    _check("residual_check", lib.residual_check(n, A.data_ptr(), lda, X.data_ptr(), ldx,
+    _check("residual_check", _lib().residual_check(n, A.data_ptr(), lda, X.data_ptr(), ldx,
                                                 B.data_ptr(), ldb, nrhs, out.data_ptr(),
                                                 _stream(stream)))
     return out
@@ -188,12 +227,12 @@ def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: i
         X = torch.empty_like(B)
     ldx = _mat(X, torch.float64, "X")
     if work is None:
-        nbytes = lib.lu_solve_ir_workspace_bytes(n, nb, p, nrhs)
+        nbytes = _lib().lu_solve_ir_workspace_bytes(n, nb, p, nrhs)
         if nbytes == 0:
             raise ValueError("unsupported solve_ir arguments")
         work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     rep = IRReport()
-    _check("lu_solve_ir", lib.lu_solve_ir(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
+    _check("lu_solve_ir", _lib().lu_solve_ir(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
                                           X.data_ptr(), ldx, nrhs, max_iter, work.data_ptr(),
                                           work.numel(), ctypes.byref(rep), _stream(stream)))
     return X, rep
@@ -208,7 +247,7 @@ def panel_factor(P: torch.Tensor, prec="fp64", work=None, stream=None):
         work = workspace(m, max(w, 1), p, P.device)
     ipiv = torch.empty(max(w, 1), dtype=torch.int32, device=P.device)
     info = torch.empty(1, dtype=torch.int32, device=P.device)
-    _check("lp_panel_factor", lib.lp_panel_factor(m, w, p, P.data_ptr(), ld, ipiv.data_ptr(),
+    _check("lp_panel_factor", _lib().lp_panel_factor(m, w, p, P.data_ptr(), ld, ipiv.data_ptr(),
                                                   info.data_ptr(), work.data_ptr(),
                                                   work.numel(), _stream(stream)))
     return ipiv, info
@@ -218,9 +257,9 @@ def laswp(A: torch.Tensor, c0: int, c1: int, k1: int, k2: int, ipiv: torch.Tenso
           stream=None) -> None:
     p = FP64 if A.dtype == torch.float64 else FP32
     lda = _mat(A, None, "A")
-    nbytes = lib.lp_laswp_workspace_bytes(k2 - k1)
+    nbytes = _lib().lp_laswp_workspace_bytes(k2 - k1)
     work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=A.device)
-    _check("lp_laswp", lib.lp_laswp(p, A.data_ptr(), lda, c0, c1, k1, k2, ipiv.data_ptr(),
+    _check("lp_laswp", _lib().lp_laswp(p, A.data_ptr(), lda, c0, c1, k1, k2, ipiv.data_ptr(),
                                     work.data_ptr(), work.numel(), _stream(stream)))
 
 
@@ -228,8 +267,12 @@ def trsm_lower_unit(L: torch.Tensor, B: torch.Tensor, stream=None) -> None:
     p = FP64 if B.dtype == torch.float64 else FP32
     ldl = _mat(L, B.dtype, "L")
     ldb = _mat(B, B.dtype, "B")
-    _check("lp_trsm_lower_unit", lib.lp_trsm_lower_unit(p, B.shape[0], B.shape[1], L.data_ptr(),
-                                                        ldl, B.data_ptr(), ldb, _stream(stream)))
+    m = B.shape[0]
+    nbytes = _lib().lp_trsm_workspace_bytes(m)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=B.device)
+    _check("lp_trsm_lower_unit", _lib().lp_trsm_lower_unit(p, m, B.shape[1], L.data_ptr(), ldl,
+                                                           B.data_ptr(), ldb, work.data_ptr(),
+                                                           work.numel(), _stream(stream)))
 
 
 def gemm_update(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=None,
@@ -246,7 +289,7 @@ def gemm_update(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=None,
     N = B.shape[1]
     if B.shape[0] != K or C.shape != (M, N):
         raise ValueError("shape mismatch")
-    _check("lp_gemm_update", lib.lp_gemm_update(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
+    _check("lp_gemm_update", _lib().lp_gemm_update(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
                                                 C.data_ptr(), ldc, _stream(stream)))
 
 
@@ -254,7 +297,7 @@ def convert(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
     to_f32 = 1 if src.dtype == torch.float64 else 0
     lds = _mat(src, None, "src")
     ldd = _mat(dst, None, "dst")
-    _check("lp_convert", lib.lp_convert(to_f32, src.shape[0], src.shape[1], src.data_ptr(), lds,
+    _check("lp_convert", _lib().lp_convert(to_f32, src.shape[0], src.shape[1], src.data_ptr(), lds,
                                         dst.data_ptr(), ldd, _stream(stream)))
 
 

@@ -35,14 +35,19 @@ int num_cus();
 // All launchers return LP_OK or LP_EHIP_BASE - hipError.  Arguments are
 // assumed valid (checked by the C ABI layer).
 
-// C := C - A B (row-major, prec as lp_prec).
+// C := C - A B (row-major, prec as lp_prec).  kind selects the kernel name
+// (trailing update or update inside a panel); the arithmetic is the same.
+constexpr int kGemmTrailing = 0;
+constexpr int kGemmPanel = 1;
 int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long lda,
-                       const void* B, long long ldb, void* C, long long ldc, hipStream_t s);
+                       const void* B, long long ldb, void* C, long long ldc, hipStream_t s,
+                       int kind = kGemmTrailing);
 
-// B := L^-1 B, L unit lower m x m.
+// B := L^-1 B, L unit lower m x m (m <= 512); work: trsm_workspace_bytes(m).
+size_t trsm_workspace_bytes(int m);
 template <typename T>
 int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
-                           hipStream_t s);
+                           void* work, hipStream_t s);
 
 // Swap plan for interchanges k1..k2-1 (device ipiv, absolute rows): writes a
 // gather list (dst, src) into plan; see panel.hip.

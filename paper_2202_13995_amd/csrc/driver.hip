@@ -60,7 +60,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout of lu_factor (offsets in bytes).
 struct FactorLayout {
-  size_t barriers, n_barriers, slots, plan_panel, plan_trail, total;
+  size_t barriers, n_barriers, slots, plan_panel, plan_trail, linv_panel, linv_trail, total;
 };
 
 FactorLayout factor_layout(int n, int nb) {
@@ -76,6 +76,10 @@ FactorLayout factor_layout(int n, int nb) {
   off = align_up(off + swap_plan_bytes(kMaxNb), 256);
   L.plan_trail = off;
   off = align_up(off + swap_plan_bytes(kMaxNb), 256);
+  L.linv_panel = off;
+  off = align_up(off + trsm_workspace_bytes(256), 256);
+  L.linv_trail = off;
+  off = align_up(off + trsm_workspace_bytes(256), 256);
   L.total = off;
   return L;
 }
@@ -95,6 +99,7 @@ struct Factor {
   int n_barriers;
   int next_barrier;
   void* plan_panel;
+  void* linv;
   hipStream_t s;
 
   T* at(long long i, long long j) const { return A + i * lda + j; }
@@ -122,13 +127,14 @@ struct Factor {
     int rc = panel(j0, w1);
     if (rc != LP_OK) return rc;
     if ((rc = swaps(j0, j0 + w1, j0 + w1, j0 + w)) != LP_OK) return rc;
-    if ((rc = launch_trsm_lower_unit<T>(w1, w2, at(j0, j0), lda, at(j0, j0 + w1), lda, s)) !=
-        LP_OK)
+    if ((rc = launch_trsm_lower_unit<T>(w1, w2, at(j0, j0), lda, at(j0, j0 + w1), lda, linv,
+                                        s)) != LP_OK)
       return rc;
     const int mrest = m - j0 - w1;
     if (mrest > 0) {
       if ((rc = launch_gemm_update(prec_for_gemm(), mrest, w2, w1, at(j0 + w1, j0), lda,
-                                   at(j0, j0 + w1), lda, at(j0 + w1, j0 + w1), lda, s)) != LP_OK)
+                                   at(j0, j0 + w1), lda, at(j0 + w1, j0 + w1), lda, s,
+                                   kGemmPanel)) != LP_OK)
         return rc;
     }
     if ((rc = panel(j0 + w1, w2)) != LP_OK) return rc;
@@ -139,35 +145,185 @@ struct Factor {
   int prec_for_gemm() const { return sizeof(T) == 8 ? LP_FP64 : LP_FP32; }
 };
 
+// Optional per-phase timing: HIP events bracket every launch group on the
+// stream that runs it; read back after the call synchronizes.
+struct Prof {
+  bool on = false;
+  struct Span {
+    hipEvent_t a, b;
+  };
+  std::vector<Span> gemm, panel, swap, trsm;
+  double gemm_flops = 0, gemm_bytes = 0, swap_bytes = 0, trsm_flops = 0;
+
+  int begin(std::vector<Span>& v, hipStream_t s) {
+    if (!on) return LP_OK;
+    Span sp;
+    LP_HIP_TRY(hipEventCreate(&sp.a));
+    LP_HIP_TRY(hipEventCreate(&sp.b));
+    LP_HIP_TRY(hipEventRecord(sp.a, s));
+    v.push_back(sp);
+    return LP_OK;
+  }
+  int end(std::vector<Span>& v, hipStream_t s) {
+    if (!on) return LP_OK;
+    LP_HIP_TRY(hipEventRecord(v.back().b, s));
+    return LP_OK;
+  }
+  static double total(std::vector<Span>& v) {
+    double t = 0;
+    for (auto& sp : v) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) t += ms;
+    }
+    return t;
+  }
+  void release() {
+    for (auto* v : {&gemm, &panel, &swap, &trsm})
+      for (auto& sp : *v) {
+        (void)hipEventDestroy(sp.a);
+        (void)hipEventDestroy(sp.b);
+      }
+  }
+};
+
+// RAII holder for the look-ahead stream and its events.
+struct Lookahead {
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+  ~Lookahead() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (s2) (void)hipStreamDestroy(s2);
+  }
+  int event(hipEvent_t* out) {
+    hipEvent_t e;
+    LP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+    *out = e;
+    return LP_OK;
+  }
+};
+
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
-                char* work, hipStream_t s) {
+                char* work, hipStream_t s, bool lookahead, Prof& prof) {
   const FactorLayout L = factor_layout(n, nb);
   int rc = launch_zero_words(info, 1, s);
   if (rc != LP_OK) return rc;
   if (n == 0) return LP_OK;
   if ((rc = launch_zero_words(work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
-  Factor<T> f{n,       A,    lda,   ipiv, info, prec, work + L.slots, (unsigned*)(work + L.barriers),
-              (int)L.n_barriers, 0, work + L.plan_panel, s};
+  Factor<T> f{n, A, lda, ipiv, info, prec, work + L.slots, (unsigned*)(work + L.barriers),
+              (int)L.n_barriers, 0, work + L.plan_panel, work + L.linv_panel, s};
+  void* linv_trail = work + L.linv_trail;
   void* plan_trail = work + L.plan_trail;
-  for (int j0 = 0; j0 < n; j0 += nb) {
-    const int w = std::min(nb, n - j0);
-    if ((rc = f.panel(j0, w)) != LP_OK) return rc;
+  const int npanels = (int)cdiv(n, nb);
+  Lookahead la;
+  if (lookahead && npanels > 1) {
+    LP_HIP_TRY(hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking));
+  }
+  const double es = sizeof(T);
+
+  // trailing steps of panel k on stream s over the column range [c0, c1) right of
+  // the panel (and, if left, the columns left of the panel for the exchanges)
+  auto trailing = [&](int j0, int w, int c0, int c1, bool left) -> int {
     const int j1 = j0 + w;
+    int r;
+    if ((r = prof.begin(prof.swap, s)) != LP_OK) return r;
+    if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, s)) != LP_OK)
+      return r;
+    if ((r = prof.end(prof.swap, s)) != LP_OK) return r;
+    prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
+    if (c1 <= c0) return LP_OK;
+    if ((r = prof.begin(prof.trsm, s)) != LP_OK) return r;
+    if ((r = launch_trsm_lower_unit<T>(w, c1 - c0, f.at(j0, j0), lda, f.at(j0, c0), lda,
+                                       linv_trail, s)) != LP_OK)
+      return r;
+    if ((r = prof.end(prof.trsm, s)) != LP_OK) return r;
+    prof.trsm_flops += 1.0 * w * w * (c1 - c0);
+    const int M = n - j1, N = c1 - c0;
+    if (M <= 0) return LP_OK;
+    if ((r = prof.begin(prof.gemm, s)) != LP_OK) return r;
+    if ((r = launch_gemm_update(prec, M, N, w, f.at(j1, j0), lda, f.at(j0, c0), lda,
+                                f.at(j1, c0), lda, s)) != LP_OK)
+      return r;
+    if ((r = prof.end(prof.gemm, s)) != LP_OK) return r;
+    prof.gemm_flops += 2.0 * M * N * w;
+    prof.gemm_bytes += es * (2.0 * M * N + (double)M * w + (double)w * N);
+    return LP_OK;
+  };
+
+  // panel 0 on the caller's stream
+  if ((rc = prof.begin(prof.panel, s)) != LP_OK) return rc;
+  if ((rc = f.panel(0, std::min(nb, n))) != LP_OK) return rc;
+  if ((rc = prof.end(prof.panel, s)) != LP_OK) return rc;
+  hipEvent_t panel_done = nullptr;  // event after the current panel (look-ahead stream)
+  for (int k = 0; k < npanels; ++k) {
+    const int j0 = k * nb;
+    const int w = std::min(nb, n - j0);
+    const int j1 = j0 + w;
+    if (panel_done) LP_HIP_TRY(hipStreamWaitEvent(s, panel_done, 0));
     if (j0 > 0 || j1 < n) {
       if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, s)) != LP_OK) return rc;
-      if ((rc = launch_swap_apply<T>(A, lda, j1, n, 0, j0, w, plan_trail, s)) != LP_OK) return rc;
     }
-    if (j1 < n) {
-      if ((rc = launch_trsm_lower_unit<T>(w, n - j1, f.at(j0, j0), lda, f.at(j0, j1), lda, s)) !=
-          LP_OK)
-        return rc;
-      if ((rc = launch_gemm_update(prec, n - j1, n - j1, w, f.at(j1, j0), lda, f.at(j0, j1), lda,
-                                   f.at(j1, j1), lda, s)) != LP_OK)
-        return rc;
+    const bool more = k + 1 < npanels;
+    const int w2 = more ? std::min(nb, n - j1) : 0;
+    if (more && la.s2) {
+      // the next panel's columns first, then factor it beside the rest
+      if ((rc = trailing(j0, w, j1, j1 + w2, false)) != LP_OK) return rc;
+      hipEvent_t next_ready;
+      if ((rc = la.event(&next_ready)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(next_ready, s));
+      LP_HIP_TRY(hipStreamWaitEvent(la.s2, next_ready, 0));
+      f.s = la.s2;
+      if ((rc = prof.begin(prof.panel, la.s2)) != LP_OK) return rc;
+      if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
+      if ((rc = prof.end(prof.panel, la.s2)) != LP_OK) return rc;
+      f.s = s;
+      if ((rc = la.event(&panel_done)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(panel_done, la.s2));
+      if ((rc = trailing(j0, w, j1 + w2, n, true)) != LP_OK) return rc;
+    } else {
+      if ((rc = trailing(j0, w, j1, n, true)) != LP_OK) return rc;
+      if (more) {
+        if ((rc = prof.begin(prof.panel, s)) != LP_OK) return rc;
+        if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
+        if ((rc = prof.end(prof.panel, s)) != LP_OK) return rc;
+      }
+      panel_done = nullptr;
     }
   }
+  if (la.s2) {
+    // nothing may remain on the look-ahead stream past this point; make that explicit
+    hipEvent_t joined;
+    if ((rc = la.event(&joined)) != LP_OK) return rc;
+    LP_HIP_TRY(hipEventRecord(joined, la.s2));
+    LP_HIP_TRY(hipStreamWaitEvent(s, joined, 0));
+  }
   return LP_OK;
+}
+
+template <typename T>
+int factor_entry(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
+                 char* work, hipStream_t s, bool lookahead, lp_factor_profile* out) {
+  Prof prof;
+  prof.on = out != nullptr;
+  int rc = factor_impl<T>(n, nb, prec, A, lda, ipiv, info, work, s, lookahead, prof);
+  if (out != nullptr) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc == LP_OK && e != hipSuccess) rc = LP_EHIP_BASE - (int)e;
+    std::memset(out, 0, sizeof(*out));
+    out->gemm_launches = (int)prof.gemm.size();
+    out->gemm_ms = Prof::total(prof.gemm);
+    out->gemm_flops = prof.gemm_flops;
+    out->gemm_bytes = prof.gemm_bytes;
+    out->panel_ms = Prof::total(prof.panel);
+    out->panel_launches = (int)prof.panel.size();
+    out->swap_ms = Prof::total(prof.swap);
+    out->swap_bytes = prof.swap_bytes;
+    out->trsm_ms = Prof::total(prof.trsm);
+    out->trsm_flops = prof.trsm_flops;
+  }
+  prof.release();
+  return rc;
 }
 
 }  // namespace
@@ -196,8 +352,9 @@ size_t lu_workspace_bytes(int n, int nb, int prec) {
   return factor_layout(n, nb).total;
 }
 
-int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info, void* work,
-              size_t work_bytes, void* stream) {
+int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
+                 void* work, size_t work_bytes, const lp_factor_opts* opts,
+                 lp_factor_profile* prof, void* stream) {
   if (n < 0) return -1;
   if (n > kMaxN) return LP_ENOTSUP;
   if (nb < 1 || nb > kMaxNb) return -2;
@@ -208,10 +365,18 @@ int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t*
   if (info == nullptr) return -7;
   if (work == nullptr) return -8;
   if (work_bytes < lu_workspace_bytes(n, nb, prec)) return LP_ENOSPC;
+  const bool lookahead = opts == nullptr || opts->lookahead != 0;
   hipStream_t s = (hipStream_t)stream;
   if (prec == LP_FP64)
-    return factor_impl<double>(n, nb, prec, (double*)A, lda, ipiv, info, (char*)work, s);
-  return factor_impl<float>(n, nb, prec, (float*)A, lda, ipiv, info, (char*)work, s);
+    return factor_entry<double>(n, nb, prec, (double*)A, lda, ipiv, info, (char*)work, s,
+                                lookahead, prof);
+  return factor_entry<float>(n, nb, prec, (float*)A, lda, ipiv, info, (char*)work, s, lookahead,
+                             prof);
+}
+
+int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info, void* work,
+              size_t work_bytes, void* stream) {
+  return lu_factor_ex(n, nb, prec, A, lda, ipiv, info, work, work_bytes, nullptr, nullptr, stream);
 }
 
 int lu_solve(int n, int storage, const void* LU, int lda, const int32_t* ipiv,
@@ -265,12 +430,14 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
   if ((rc = launch_zero_words((char*)work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
   char* wk = (char*)work;
   if (prec == LP_FP64) {
-    Factor<double> f{m, (double*)A, lda, ipiv, info, prec, wk + L.slots, (unsigned*)(wk + L.barriers),
-                     (int)L.n_barriers, 0, wk + L.plan_panel, s};
+    Factor<double> f{m, (double*)A, lda, ipiv, info, prec, wk + L.slots,
+                     (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.plan_panel,
+                     wk + L.linv_panel, s};
     return f.panel(0, w);
   }
-  Factor<float> f{m, (float*)A, lda, ipiv, info, prec, wk + L.slots, (unsigned*)(wk + L.barriers),
-                  (int)L.n_barriers, 0, wk + L.plan_panel, s};
+  Factor<float> f{m, (float*)A, lda, ipiv, info, prec, wk + L.slots,
+                  (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.plan_panel,
+                  wk + L.linv_panel, s};
   return f.panel(0, w);
 }
 
@@ -300,8 +467,13 @@ int lp_laswp(int prec, void* A, int lda, int c0, int c1, int k1, int k2, const i
   return launch_swap_apply<float>((float*)A, lda, c0, c1, c1, c1, k2 - k1, work, s);
 }
 
+size_t lp_trsm_workspace_bytes(int m) {
+  if (m < 0) return 0;
+  return trsm_workspace_bytes(std::min(std::max(m, 1), 256));
+}
+
 int lp_trsm_lower_unit(int prec, int m, int ncols, const void* L, int ldl, void* B, int ldb,
-                       void* stream) {
+                       void* work, size_t work_bytes, void* stream) {
   if (!valid_prec(prec)) return -1;
   if (m < 0) return -2;
   if (ncols < 0) return -3;
@@ -309,10 +481,13 @@ int lp_trsm_lower_unit(int prec, int m, int ncols, const void* L, int ldl, void*
   if (ldl < std::max(1, m)) return -5;
   if (B == nullptr && m > 0 && ncols > 0) return -6;
   if (ldb < std::max(1, ncols)) return -7;
+  if (work == nullptr) return -8;
+  if (work_bytes < lp_trsm_workspace_bytes(m)) return LP_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
   if (prec == LP_FP64)
-    return launch_trsm_lower_unit<double>(m, ncols, (const double*)L, ldl, (double*)B, ldb, s);
-  return launch_trsm_lower_unit<float>(m, ncols, (const float*)L, ldl, (float*)B, ldb, s);
+    return launch_trsm_lower_unit<double>(m, ncols, (const double*)L, ldl, (double*)B, ldb, work,
+                                          s);
+  return launch_trsm_lower_unit<float>(m, ncols, (const float*)L, ldl, (float*)B, ldb, work, s);
 }
 
 int lp_gemm_update(int prec, int M, int N, int K, const void* A, int lda, const void* B, int ldb,

@@ -52,7 +52,7 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
   tn = within / gm;
 }
 
-__global__ __launch_bounds__(256, 2) void dgemm_update_kernel(
+__device__ __forceinline__ void dgemm_update_body(
     int M, int N, int K, const double* __restrict__ A, long long lda,
     const double* __restrict__ B, long long ldb, double* __restrict__ C, long long ldc,
     int tiles_m, int tiles_n) {
@@ -158,19 +158,41 @@ __global__ __launch_bounds__(256, 2) void dgemm_update_kernel(
   }
 }
 
+// The trailing-matrix update and the updates inside a panel run the same body
+// under two names so that traces separate them.
+__global__ __launch_bounds__(256, 2) void dgemm_trailing_update(
+    int M, int N, int K, const double* __restrict__ A, long long lda,
+    const double* __restrict__ B, long long ldb, double* __restrict__ C, long long ldc,
+    int tiles_m, int tiles_n) {
+  dgemm_update_body(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+}
+
+__global__ __launch_bounds__(256, 2) void dgemm_panel_update(
+    int M, int N, int K, const double* __restrict__ A, long long lda,
+    const double* __restrict__ B, long long ldb, double* __restrict__ C, long long ldc,
+    int tiles_m, int tiles_n) {
+  dgemm_update_body(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+}
+
 }  // namespace
 
 int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long lda,
-                       const void* B, long long ldb, void* C, long long ldc, hipStream_t s) {
+                       const void* B, long long ldb, void* C, long long ldc, hipStream_t s,
+                       int kind) {
   if (M <= 0 || N <= 0 || K <= 0) return LP_OK;
   if (prec == LP_FP64) {
     const int tiles_m = (int)cdiv(M, DBM);
     const int tiles_n = (int)cdiv(N, DBN);
     const long long T = (long long)tiles_m * tiles_n;
     if (T > 0x7fffffffLL) return LP_ENOTSUP;
-    hipLaunchKernelGGL(dgemm_update_kernel, dim3((unsigned)T), dim3(256), 0, s, M, N, K,
-                       (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, tiles_m,
-                       tiles_n);
+    if (kind == kGemmPanel)
+      hipLaunchKernelGGL(dgemm_panel_update, dim3((unsigned)T), dim3(256), 0, s, M, N, K,
+                         (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, tiles_m,
+                         tiles_n);
+    else
+      hipLaunchKernelGGL(dgemm_trailing_update, dim3((unsigned)T), dim3(256), 0, s, M, N, K,
+                         (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, tiles_m,
+                         tiles_n);
     LP_LAUNCH_CHECK();
     return LP_OK;
   }

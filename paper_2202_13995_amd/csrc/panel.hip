@@ -66,17 +66,32 @@ int launch_convert(int to_f32, int rows, int cols, const void* src, long long ld
 // other kernel depends on this one), so the wait ends; it is still bounded by
 // the device's constant 100 MHz clock so that a stuck launch drains instead of
 // hanging.  Returns false on timeout.
+//
+// Cross-workgroup data goes through relaxed agent-scope atomic loads and
+// stores, which the compiler emits as L2-coherent (sc1) accesses; each thread
+// waits for its own stores to be acknowledged before the workgroup arrives.
+// This avoids release/acquire fences, which on this chip write back and
+// invalidate the whole L2 of the compute die and would stall the concurrent
+// trailing update.
 constexpr unsigned long long kBarrierTimeoutTicks = 2000000000ull;  // 20 s at 100 MHz
 
+template <typename V>
+__device__ __forceinline__ void xstore(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ V xload(const V* p) {
+  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ bool grid_barrier(unsigned* ctr, unsigned target, int* s_flag) {
-  // make this thread's global writes visible device-wide before arriving
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have landed
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     int ok = 1;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (xload(ctr) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
         ok = 0;
@@ -86,7 +101,6 @@ __device__ bool grid_barrier(unsigned* ctr, unsigned target, int* s_flag) {
     *s_flag = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_flag != 0;
 }
 
@@ -228,15 +242,17 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(int m, int j0, int w,
           const T v = tile[jj * R + (cand - base)];
           kk = (v != v) ? -1.0 : fabs((double)v);
         }
-        skey[g] = kk;
-        sidx[g] = cand;
+        xstore(&skey[g], kk);
+        xstore(&sidx[g], cand);
       }
-      if (tid < w) srows[(size_t)g * kLeafMax + tid] = (cand != INT_MAX) ? tile[tid * R + (cand - base)] : T(0);
+      if (tid < w)
+        xstore(&srows[(size_t)g * kLeafMax + tid],
+               (cand != INT_MAX) ? tile[tid * R + (cand - base)] : T(0));
       if (dg >= base && dg < base + nrows) {
-        if (tid < w) sdiag[tid] = tile[tid * R + (dg - base)];
+        if (tid < w) xstore(&sdiag[tid], tile[tid * R + (dg - base)]);
         if (tid == 0) {
           const T dv = tile[jj * R + (dg - base)];
-          *sflag = (dv != dv) ? 1 : 0;
+          xstore(sflag, (dv != dv) ? 1 : 0);
         }
       }
       // 2. everyone meets
@@ -248,8 +264,8 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(int m, int j0, int w,
       double k2 = -3.0;
       int i2 = INT_MAX;
       if (tid < G) {
-        k2 = skey[tid];
-        i2 = sidx[tid];
+        k2 = xload(&skey[tid]);
+        i2 = xload(&sidx[tid]);
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -271,14 +287,14 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(int m, int j0, int w,
             k2 = red_key[t];
             i2 = red_idx[t];
           }
-        s_p = (*sflag) ? dg : i2;
+        s_p = xload(sflag) ? dg : i2;
       }
       __syncthreads();
       const int p = s_p;
       if (tid < w) {
-        const T dv = sdiag[tid];
+        const T dv = xload(&sdiag[tid]);
         drow[tid] = dv;
-        prow[tid] = (p == dg) ? dv : srows[(size_t)((p - j0) / R) * kLeafMax + tid];
+        prow[tid] = (p == dg) ? dv : xload(&srows[(size_t)((p - j0) / R) * kLeafMax + tid]);
       }
     } else {
       // single workgroup: everything is local
@@ -456,57 +472,175 @@ template int launch_swap_apply<float>(float*, long long, int, int, int, int, int
 
 // ------------------------------------------------ unit lower triangular solve
 // B := L^-1 B, L unit lower m x m: the paper's "top blocks" update of the
-// blocks right of the diagonal block with its lower factor.  Columns of B are
-// independent; each thread owns one column and runs forward substitution over
-// blocks of 16 rows held in registers (left-looking: the rows already solved
-// are re-read from its own column, the L entries are uniform across the wave).
+// blocks right of the diagonal block with its lower factor.
+//
+// Columns of B are independent.  One wave owns a strip of 16 columns and keeps
+// the whole strip (m <= 512 rows, as 16 x 16 tiles) in registers in the MFMA
+// output layout.  Block row r is solved by multiplying with the precomputed
+// inverse of the 16 x 16 diagonal block L_rr, then subtracted from every later
+// block row (X_q -= L_qr X_r), all on the matrix cores.  For both MFMA shapes
+// used here there is an ordering of the 4-long k-steps for which output
+// register t of a lane is exactly that lane's B operand in k-step t, so solved
+// tiles feed the next products without leaving registers:
+//   FP64 16x16x4: output (lane l, reg v) = D[l/16 + 4v][l%16]; step t uses k = l/16 + 4t
+//   FP32 16x16x4: output (lane l, reg v) = D[4(l/16) + v][l%16]; step t uses k = 4(l/16) + t
+// (A operand: lane l supplies row l % 16 at that k; layouts checked on the device.)
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_lower_unit_kernel(int m, int ncols,
-                                                              const T* __restrict__ L,
-                                                              long long ldl, T* __restrict__ B,
-                                                              long long ldb) {
-  constexpr int RB = 16;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = c < ncols;
-  for (int rb = 0; rb < m; rb += RB) {
-    const int nr = min(RB, m - rb);
-    T x[RB];
+struct Mfma16;
+
+template <>
+struct Mfma16<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int g, int v) { return g + 4 * v; }
+  static __device__ __forceinline__ int kidx(int g, int t) { return g + 4 * t; }
+};
+
+template <>
+struct Mfma16<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int g, int v) { return 4 * g + v; }
+  static __device__ __forceinline__ int kidx(int g, int t) { return 4 * g + t; }
+};
+
+// Inverse of each 16 x 16 unit lower diagonal block of L (rows beyond m are
+// treated as identity).  Linv[r] is stored row-major, 256 entries per block.
+template <typename T>
+__global__ __launch_bounds__(64) void diag_block_inverse_kernel(int m, const T* __restrict__ L,
+                                                                long long ldl,
+                                                                T* __restrict__ Linv) {
+  const int r = blockIdx.x;
+  const int j = threadIdx.x;
+  __shared__ T Ls[16][17];
+  for (int e = threadIdx.x; e < 256; e += 64) {
+    const int i = e >> 4, k = e & 15;
+    const int gi = 16 * r + i, gk = 16 * r + k;
+    Ls[i][k] = (gi < m && gk < m) ? L[(long long)gi * ldl + gk] : T(0);
+  }
+  __syncthreads();
+  if (j < 16) {
+    T x[16];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) x[r] = (ok && r < nr) ? B[(long long)(rb + r) * ldb + c] : T(0);
-    for (int k = 0; k < rb; ++k) {
-      const T xk = ok ? B[(long long)k * ldb + c] : T(0);
+    for (int i = 0; i < 16; ++i) x[i] = (i == j) ? T(1) : T(0);
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
-        if (r < nr) x[r] -= L[(long long)(rb + r) * ldl + k] * xk;
+    for (int i = 1; i < 16; ++i) {
+      T acc = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc -= Ls[i][k] * x[k];
+      x[i] = acc;
     }
 #pragma unroll
-    for (int r = 1; r < RB; ++r) {
-      if (r < nr) {
-#pragma unroll
-        for (int q = 0; q < r; ++q) x[r] -= L[(long long)(rb + r) * ldl + rb + q] * x[q];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (ok && r < nr) B[(long long)(rb + r) * ldb + c] = x[r];
+    for (int i = 0; i < 16; ++i) Linv[(long long)r * 256 + i * 16 + j] = x[i];
   }
 }
 
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void trsm_mfma_kernel(int m, int ncols, const T* __restrict__ L,
+                                                        long long ldl,
+                                                        const T* __restrict__ Linv,
+                                                        T* __restrict__ B, long long ldb) {
+  typedef Mfma16<T> M;
+  typedef typename M::acc acc_t;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int c16 = lane & 15;
+  const int col = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + c16;
+  const bool colok = col < ncols;
+  const int nt = (m + 15) >> 4;
+  acc_t X[NT];
+#pragma unroll
+  for (int r = 0; r < NT; ++r) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * r + M::drow(g, v);
+      X[r][v] = (r < nt && row < m && colok) ? B[(long long)row * ldb + col] : T(0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NT; ++r) {
+    if (r < nt) {
+      acc_t Y = {0, 0, 0, 0};
+      const T* li = Linv + (long long)r * 256 + c16 * 16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Y = M::mma(li[M::kidx(g, t)], X[r][t], Y);
+      X[r] = Y;
+#pragma unroll
+      for (int q = r + 1; q < NT; ++q) {
+        if (q < nt) {
+          const int row = 16 * q + c16;
+          const T* lrow = L + (long long)row * ldl + 16 * r;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const T a = (row < m) ? -lrow[M::kidx(g, t)] : T(0);
+            X[q] = M::mma(a, X[r][t], X[q]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NT; ++r) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * r + M::drow(g, v);
+      if (r < nt && row < m && colok) B[(long long)row * ldb + col] = X[r][v];
+    }
+  }
+}
+
+size_t trsm_workspace_bytes(int m) { return sizeof(double) * 256 * (size_t)cdiv(m, 16); }
+
+// Triangles taller than 256 rows: solve the first 256 rows, subtract their
+// contribution from the rows below with the inner-block update kernel, repeat.
 template <typename T>
 int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
-                           hipStream_t s) {
+                           void* work, hipStream_t s) {
   if (m <= 0 || ncols <= 0) return LP_OK;
-  const int threads = 256;
-  const long long blocks = cdiv(ncols, threads);
-  hipLaunchKernelGGL((trsm_lower_unit_kernel<T>), dim3((unsigned)blocks), dim3(threads), 0, s, m,
-                     ncols, L, ldl, B, ldb);
-  LP_LAUNCH_CHECK();
+  constexpr int kChunk = 256;
+  for (int r0 = 0; r0 < m; r0 += kChunk) {
+    const int mc = min(kChunk, m - r0);
+    const T* Lc = L + (long long)r0 * ldl + r0;
+    T* Bc = B + (long long)r0 * ldb;
+    const int nt = (int)cdiv(mc, 16);
+    T* Linv = (T*)work;
+    hipLaunchKernelGGL((diag_block_inverse_kernel<T>), dim3(nt), dim3(64), 0, s, mc, Lc, ldl,
+                       Linv);
+    LP_LAUNCH_CHECK();
+    const dim3 grid((unsigned)cdiv(ncols, 64));
+    bool done = false;
+#define LP_TRSM_CASE(NTV)                                                                     \
+    if (!done && nt <= NTV) {                                                                 \
+      hipLaunchKernelGGL((trsm_mfma_kernel<T, NTV>), grid, dim3(256), 0, s, mc, ncols, Lc, ldl, \
+                         (const T*)Linv, Bc, ldb);                                            \
+      LP_LAUNCH_CHECK();                                                                      \
+      done = true;                                                                            \
+    }
+    LP_TRSM_CASE(1)
+    LP_TRSM_CASE(2)
+    LP_TRSM_CASE(4)
+    LP_TRSM_CASE(8)
+    LP_TRSM_CASE(16)
+#undef LP_TRSM_CASE
+    if (!done) return LP_ENOTSUP;
+    const int rest = m - r0 - mc;
+    if (rest > 0) {
+      const int prec = sizeof(T) == 8 ? LP_FP64 : LP_FP32;
+      int rc = launch_gemm_update(prec, rest, ncols, mc, L + (long long)(r0 + mc) * ldl + r0, ldl,
+                                  Bc, ldb, B + (long long)(r0 + mc) * ldb, ldb, s, kGemmPanel);
+      if (rc != LP_OK) return rc;
+    }
+  }
   return LP_OK;
 }
 
 template int launch_trsm_lower_unit<double>(int, int, const double*, long long, double*,
-                                            long long, hipStream_t);
+                                            long long, void*, hipStream_t);
 template int launch_trsm_lower_unit<float>(int, int, const float*, long long, float*, long long,
-                                           hipStream_t);
+                                           void*, hipStream_t);
 
 }  // namespace lp

@@ -84,7 +84,8 @@ def test_gemm_update_strided_views(lp):
 
 
 # ---------------------------------------------------------------------- trsm
-@pytest.mark.parametrize("m,ncols", [(1, 5), (16, 16), (17, 300), (64, 1000), (256, 333)])
+@pytest.mark.parametrize("m,ncols", [(1, 5), (16, 16), (17, 300), (64, 1000), (256, 333), (200, 7),
+                                     (512, 999), (300, 64), (33, 2)])
 def test_trsm_lower_unit(lp, m, ncols):
     rng = np.random.default_rng(m + ncols)
     L = np.tril(rng.uniform(-1, 1, (m, m)), -1) + np.eye(m)

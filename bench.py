@@ -69,6 +69,9 @@ def main() -> int:
     ap.add_argument("--no-lookahead", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-mib", type=int, default=0,
+                    help="run a plain element-wise copy-convert of this many MiB of doubles "
+                         "before the timed steps (reference for HBM traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -98,6 +101,17 @@ def main() -> int:
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     look = not args.no_lookahead
+
+    calib = None
+    if args.calib_mib > 0:
+        rows = max(1, args.calib_mib * 2**20 // (8 * n))
+        src = A0[:rows]
+        dst = torch.empty((rows, n), dtype=torch.float32, device=dev)
+        lp.convert(src, dst)
+        torch.cuda.synchronize()
+        calib = {"kernel": "convert_kernel<double,float>", "read_bytes": 8 * rows * n,
+                 "write_bytes": 4 * rows * n}
+        del dst
 
     # warm-up on a scratch copy
     scratch = torch.empty_like(A0)
@@ -175,6 +189,8 @@ def main() -> int:
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
         "phases_ms_per_step": phases,
     }
+    if calib is not None:
+        line["calibration"] = calib
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle sample n={args.cpu_n} ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed)

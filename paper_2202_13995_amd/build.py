@@ -26,8 +26,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
-SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "solve.hip", "driver.hip", "ir.hip",
-           "serve.hip"]
+SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "panel_fused.hip", "solve.hip", "driver.hip",
+           "ir.hip", "serve.hip"]
 
 
 def _run(cmd):

@@ -58,13 +58,19 @@ template <typename T>
 int launch_swap_apply(T* A, long long lda, int c0, int c1, int c2, int c3, int nswaps,
                       const void* plan, hipStream_t s);
 
-// Panel leaf: factor columns [j0, j0+w) over rows [j0, m) of A (absolute
-// indices), w <= kLeafMax.  ipiv/info absolute.  barrier: zeroed int slot.
+// Panel factorization in one launch: columns [c0, c0+W) over rows [c0, m)
+// (absolute indices), W <= 1024.  slots: leaf_slots_bytes(); barrier: one
+// zeroed 32-bit counter; staging: panel_staging_bytes(W).
 constexpr int kLeafMax = 32;
 size_t leaf_slots_bytes(int m, int w);
+size_t panel_staging_bytes(int W);
+// keys: this launch's zeroed key buffer; keys_next: the buffer of the next
+// panel launch on the same stream, which this launch zeroes.
+size_t panel_keys_bytes();
 template <typename T>
-int launch_panel_leaf(int m, int j0, int w, T* A, long long lda, int32_t* ipiv, int32_t* info,
-                      int info_base, void* slots, unsigned* barrier, hipStream_t s);
+int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
+                       void* slots, unsigned* barrier, void* staging, void* keys,
+                       void* keys_next, hipStream_t s);
 
 // Zero a range of 32-bit words (a kernel, not a memset node).
 int launch_zero_words(void* p, size_t nwords, hipStream_t s);

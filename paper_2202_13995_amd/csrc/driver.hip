@@ -60,7 +60,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout of lu_factor (offsets in bytes).
 struct FactorLayout {
-  size_t barriers, n_barriers, slots, plan_panel, plan_trail, linv_panel, linv_trail, total;
+  size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, linv_trail, total;
 };
 
 FactorLayout factor_layout(int n, int nb) {
@@ -72,12 +72,14 @@ FactorLayout factor_layout(int n, int nb) {
   off = align_up(off + 4 * L.n_barriers, 256);
   L.slots = off;
   off = align_up(off + leaf_slots_bytes(n, kLeafMax), 256);
-  L.plan_panel = off;
-  off = align_up(off + swap_plan_bytes(kMaxNb), 256);
+  L.staging = off;
+  off = align_up(off + panel_staging_bytes(kMaxNb), 256);
+  L.keys0 = off;
+  off = align_up(off + panel_keys_bytes(), 256);
+  L.keys1 = off;
+  off = align_up(off + panel_keys_bytes(), 256);
   L.plan_trail = off;
   off = align_up(off + swap_plan_bytes(kMaxNb), 256);
-  L.linv_panel = off;
-  off = align_up(off + trsm_workspace_bytes(256), 256);
   L.linv_trail = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
   L.total = off;
@@ -93,56 +95,24 @@ struct Factor {
   long long lda;
   int32_t* ipiv;
   int32_t* info;
-  int prec;
   char* slots;
   unsigned* barriers;
   int n_barriers;
   int next_barrier;
-  void* plan_panel;
-  void* linv;
+  void* staging;
+  void* keys[2];  // per-launch key buffers, alternating; the first starts zeroed
   hipStream_t s;
 
   T* at(long long i, long long j) const { return A + i * lda + j; }
 
-  int leaf(int j0, int w) {
-    if (next_barrier >= n_barriers) return LP_ENOTSUP;
-    unsigned* bar = barriers + next_barrier++;
-    return launch_panel_leaf<T>(m, j0, w, A, lda, ipiv, info, 0, slots, bar, s);
-  }
-
-  // exchange rows per ipiv[k1..k2) over columns [c0, c1)
-  int swaps(int k1, int k2, int c0, int c1) {
-    if (k2 <= k1 || c1 <= c0) return LP_OK;
-    int rc = launch_swap_plan(ipiv, k1, k2, plan_panel, s);
-    if (rc != LP_OK) return rc;
-    return launch_swap_apply<T>(A, lda, c0, c1, c1, c1, k2 - k1, plan_panel, s);
-  }
-
-  // factor columns [j0, j0 + w) over rows [j0, m)
+  // factor columns [j0, j0 + w) over rows [j0, m): one launch
   int panel(int j0, int w) {
-    if (w <= kLeafMax) return leaf(j0, w);
-    int w1 = w / 2;
-    w1 = std::max(kLeafMax, (w1 / kLeafMax) * kLeafMax);
-    const int w2 = w - w1;
-    int rc = panel(j0, w1);
-    if (rc != LP_OK) return rc;
-    if ((rc = swaps(j0, j0 + w1, j0 + w1, j0 + w)) != LP_OK) return rc;
-    if ((rc = launch_trsm_lower_unit<T>(w1, w2, at(j0, j0), lda, at(j0, j0 + w1), lda, linv,
-                                        s)) != LP_OK)
-      return rc;
-    const int mrest = m - j0 - w1;
-    if (mrest > 0) {
-      if ((rc = launch_gemm_update(prec_for_gemm(), mrest, w2, w1, at(j0 + w1, j0), lda,
-                                   at(j0, j0 + w1), lda, at(j0 + w1, j0 + w1), lda, s,
-                                   kGemmPanel)) != LP_OK)
-        return rc;
-    }
-    if ((rc = panel(j0 + w1, w2)) != LP_OK) return rc;
-    return swaps(j0 + w1, j0 + w, j0, j0 + w1);
+    if (next_barrier >= n_barriers) return LP_ENOTSUP;
+    const int idx = next_barrier++;
+    unsigned* bar = barriers + idx;
+    return launch_panel_fused<T>(m, j0, w, A, lda, ipiv, info, slots, bar, staging,
+                                 keys[idx & 1], keys[(idx + 1) & 1], s);
   }
-
-  // The panel's own multiplications stay in the storage precision.
-  int prec_for_gemm() const { return sizeof(T) == 8 ? LP_FP64 : LP_FP32; }
 };
 
 // Optional per-phase timing: HIP events bracket every launch group on the
@@ -211,8 +181,9 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   if (rc != LP_OK) return rc;
   if (n == 0) return LP_OK;
   if ((rc = launch_zero_words(work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
-  Factor<T> f{n, A, lda, ipiv, info, prec, work + L.slots, (unsigned*)(work + L.barriers),
-              (int)L.n_barriers, 0, work + L.plan_panel, work + L.linv_panel, s};
+  if ((rc = launch_zero_words(work + L.keys0, panel_keys_bytes() / 4, s)) != LP_OK) return rc;
+  Factor<T> f{n, A, lda, ipiv, info, work + L.slots, (unsigned*)(work + L.barriers),
+              (int)L.n_barriers, 0, work + L.staging, {work + L.keys0, work + L.keys1}, s};
   void* linv_trail = work + L.linv_trail;
   void* plan_trail = work + L.plan_trail;
   const int npanels = (int)cdiv(n, nb);
@@ -429,15 +400,16 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
   if (rc != LP_OK || w == 0) return rc;
   if ((rc = launch_zero_words((char*)work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
   char* wk = (char*)work;
+  if ((rc = launch_zero_words(wk + L.keys0, panel_keys_bytes() / 4, s)) != LP_OK) return rc;
   if (prec == LP_FP64) {
-    Factor<double> f{m, (double*)A, lda, ipiv, info, prec, wk + L.slots,
-                     (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.plan_panel,
-                     wk + L.linv_panel, s};
+    Factor<double> f{m, (double*)A, lda, ipiv, info, wk + L.slots,
+                     (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.staging,
+                     {wk + L.keys0, wk + L.keys1}, s};
     return f.panel(0, w);
   }
-  Factor<float> f{m, (float*)A, lda, ipiv, info, prec, wk + L.slots,
-                  (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.plan_panel,
-                  wk + L.linv_panel, s};
+  Factor<float> f{m, (float*)A, lda, ipiv, info, wk + L.slots,
+                  (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.staging,
+                  {wk + L.keys0, wk + L.keys1}, s};
   return f.panel(0, w);
 }
 

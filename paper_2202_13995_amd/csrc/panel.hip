@@ -11,6 +11,7 @@
 #include <climits>
 
 #include "common.h"
+#include "device.h"
 #include "swap_plan.h"
 
 namespace lp {
@@ -60,312 +61,13 @@ int launch_convert(int to_f32, int rows, int cols, const void* src, long long ld
   return LP_OK;
 }
 
-// --------------------------------------------------------- grid barrier
-// All workgroups of a launch meet here.  Every workgroup is resident at once
-// (the launcher keeps the grid at most one workgroup per compute unit, and no
-// other kernel depends on this one), so the wait ends; it is still bounded by
-// the device's constant 100 MHz clock so that a stuck launch drains instead of
-// hanging.  Returns false on timeout.
-//
-// Cross-workgroup data goes through relaxed agent-scope atomic loads and
-// stores, which the compiler emits as L2-coherent (sc1) accesses; each thread
-// waits for its own stores to be acknowledged before the workgroup arrives.
-// This avoids release/acquire fences, which on this chip write back and
-// invalidate the whole L2 of the compute die and would stall the concurrent
-// trailing update.
-constexpr unsigned long long kBarrierTimeoutTicks = 2000000000ull;  // 20 s at 100 MHz
-
-template <typename V>
-__device__ __forceinline__ void xstore(V* p, V v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename V>
-__device__ __forceinline__ V xload(const V* p) {
-  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ bool grid_barrier(unsigned* ctr, unsigned target, int* s_flag) {
-  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have landed
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-    int ok = 1;
-    while (xload(ctr) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
-        ok = 0;
-        break;
-      }
-    }
-    *s_flag = ok;
-  }
-  __syncthreads();
-  return *s_flag != 0;
-}
-
-// ------------------------------------------------------------- panel leaf
-// Factors columns [j0, j0 + w) of rows [j0, m) with partial pivoting, w <= 32.
-// Workgroup g owns rows [j0 + g R, j0 + (g + 1) R) and keeps their w entries in
-// LDS (column-major, R rows per column).  Per column:
-//   1. each workgroup finds its candidate: the largest |a| among its active
-//      rows (a NaN counts as smaller than every number), lowest row on ties;
-//      it publishes the candidate's key, row index and w values, and the owner
-//      of the diagonal row publishes that row;
-//   2. grid barrier;
-//   3. every workgroup reduces the G candidates the same way (so the winner is
-//      the lowest-index maximum), keeps the diagonal row if its entry is NaN
-//      (a strict '>' scan never leaves a NaN start), exchanges the two rows in
-//      its LDS if it owns them, then scales its rows below the diagonal by the
-//      pivot (a division) and applies the rank-1 update to the remaining
-//      columns of the leaf.
-// Slots are double-buffered by column parity: a workgroup can only overwrite a
-// buffer after every workgroup has passed the next barrier.
-
-struct LeafLayout {
-  size_t key_off, idx_off, rows_off, diag_off, flag_off, buf_bytes;
-};
-
-template <typename T>
-__host__ __device__ inline LeafLayout leaf_layout(int G) {
-  LeafLayout L;
-  size_t off = 0;
-  L.key_off = off;
-  off += sizeof(double) * (size_t)G;
-  L.idx_off = off;
-  off += sizeof(int) * (size_t)G;
-  off = (off + 15) & ~(size_t)15;
-  L.rows_off = off;
-  off += sizeof(T) * (size_t)G * kLeafMax;
-  L.diag_off = off;
-  off += sizeof(T) * kLeafMax;
-  L.flag_off = off;
-  off += 16;
-  off = (off + 255) & ~(size_t)255;
-  L.buf_bytes = off;
-  return L;
-}
-
+// ----------------------------------------------------- candidate slots
 size_t leaf_slots_bytes(int m, int w) {
   (void)m;
   (void)w;
   // G <= 1024 workgroups, double-sized entries (covers float too)
   return 2 * leaf_layout<double>(1024).buf_bytes;
 }
-
-__device__ __forceinline__ bool better(double ka, int ia, double kb, int ib) {
-  // is (ka, ia) a better pivot candidate than (kb, ib)?
-  return ka > kb || (ka == kb && ia < ib);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void panel_leaf_kernel(int m, int j0, int w,
-                                                         T* __restrict__ A, long long lda,
-                                                         int32_t* __restrict__ ipiv,
-                                                         int32_t* __restrict__ info, int R,
-                                                         int G, char* __restrict__ slots,
-                                                         unsigned* __restrict__ barrier) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);  // [w][R]
-  __shared__ double red_key[4];
-  __shared__ int red_idx[4];
-  __shared__ T prow[kLeafMax];
-  __shared__ T drow[kLeafMax];
-  __shared__ int s_p;
-  __shared__ int s_flag;
-
-  const LeafLayout lay = leaf_layout<T>(G);
-  const int g = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int base = j0 + g * R;
-  const int nrows = min(R, m - base);
-
-  for (int e = tid; e < nrows * w; e += blockDim.x) {
-    const int r = e / w;
-    const int c = e - r * w;
-    tile[c * R + r] = A[(long long)(base + r) * lda + j0 + c];
-  }
-  __syncthreads();
-
-  for (int jj = 0; jj < w; ++jj) {
-    const int dg = j0 + jj;  // diagonal row (global)
-    char* sb = slots + (size_t)(jj & 1) * lay.buf_bytes;
-    double* skey = reinterpret_cast<double*>(sb + lay.key_off);
-    int* sidx = reinterpret_cast<int*>(sb + lay.idx_off);
-    T* srows = reinterpret_cast<T*>(sb + lay.rows_off);
-    T* sdiag = reinterpret_cast<T*>(sb + lay.diag_off);
-    int* sflag = reinterpret_cast<int*>(sb + lay.flag_off);
-
-    // 1. local candidate
-    double bk = -2.0;
-    int bi = INT_MAX;
-    for (int r = tid; r < nrows; r += blockDim.x) {
-      const int gi = base + r;
-      if (gi >= dg) {
-        const T v = tile[jj * R + r];
-        const double k = (v != v) ? -1.0 : fabs((double)v);
-        if (better(k, gi, bk, bi)) {
-          bk = k;
-          bi = gi;
-        }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ok = __shfl_xor(bk, off);
-      const int oi = __shfl_xor(bi, off);
-      if (better(ok, oi, bk, bi)) {
-        bk = ok;
-        bi = oi;
-      }
-    }
-    if ((tid & 63) == 0) {
-      red_key[tid >> 6] = bk;
-      red_idx[tid >> 6] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int t = 1; t < 4; ++t)
-        if (better(red_key[t], red_idx[t], bk, bi)) {
-          bk = red_key[t];
-          bi = red_idx[t];
-        }
-      s_p = bi;
-    }
-    __syncthreads();
-    const int cand = s_p;
-    __syncthreads();
-    if (G > 1) {
-      if (tid == 0) {
-        double kk = -2.0;
-        if (cand != INT_MAX) {
-          const T v = tile[jj * R + (cand - base)];
-          kk = (v != v) ? -1.0 : fabs((double)v);
-        }
-        xstore(&skey[g], kk);
-        xstore(&sidx[g], cand);
-      }
-      if (tid < w)
-        xstore(&srows[(size_t)g * kLeafMax + tid],
-               (cand != INT_MAX) ? tile[tid * R + (cand - base)] : T(0));
-      if (dg >= base && dg < base + nrows) {
-        if (tid < w) xstore(&sdiag[tid], tile[tid * R + (dg - base)]);
-        if (tid == 0) {
-          const T dv = tile[jj * R + (dg - base)];
-          xstore(sflag, (dv != dv) ? 1 : 0);
-        }
-      }
-      // 2. everyone meets
-      if (!grid_barrier(barrier, (unsigned)G * (unsigned)(jj + 1), &s_flag)) {
-        if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
-        return;
-      }
-      // 3. global winner
-      double k2 = -3.0;
-      int i2 = INT_MAX;
-      if (tid < G) {
-        k2 = xload(&skey[tid]);
-        i2 = xload(&sidx[tid]);
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ok = __shfl_xor(k2, off);
-        const int oi = __shfl_xor(i2, off);
-        if (better(ok, oi, k2, i2)) {
-          k2 = ok;
-          i2 = oi;
-        }
-      }
-      if ((tid & 63) == 0) {
-        red_key[tid >> 6] = k2;
-        red_idx[tid >> 6] = i2;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        for (int t = 1; t < 4; ++t)
-          if (better(red_key[t], red_idx[t], k2, i2)) {
-            k2 = red_key[t];
-            i2 = red_idx[t];
-          }
-        s_p = xload(sflag) ? dg : i2;
-      }
-      __syncthreads();
-      const int p = s_p;
-      if (tid < w) {
-        const T dv = xload(&sdiag[tid]);
-        drow[tid] = dv;
-        prow[tid] = (p == dg) ? dv : xload(&srows[(size_t)((p - j0) / R) * kLeafMax + tid]);
-      }
-    } else {
-      // single workgroup: everything is local
-      if (tid == 0) {
-        const T dv = tile[jj * R + (dg - base)];
-        s_p = (dv != dv) ? dg : cand;
-      }
-      __syncthreads();
-      const int p = s_p;
-      if (tid < w) {
-        drow[tid] = tile[tid * R + (dg - base)];
-        prow[tid] = tile[tid * R + (p - base)];
-      }
-    }
-    __syncthreads();
-    const int p = s_p;
-    const T piv = prow[jj];
-    if (g == 0 && tid == 0) {
-      ipiv[dg] = p;
-      if (piv == T(0) && *info == 0) *info = dg + 1;
-    }
-    // exchange rows dg and p inside this workgroup's LDS
-    if (p != dg && tid < w) {
-      if (p >= base && p < base + nrows) tile[tid * R + (p - base)] = drow[tid];
-      if (dg >= base && dg < base + nrows) tile[tid * R + (dg - base)] = prow[tid];
-    }
-    __syncthreads();
-    if (piv != T(0)) {
-      for (int r = tid; r < nrows; r += blockDim.x) {
-        if (base + r > dg) {
-          const T l = tile[jj * R + r] / piv;
-          tile[jj * R + r] = l;
-          for (int c = jj + 1; c < w; ++c) tile[c * R + r] -= l * prow[c];
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  for (int e = tid; e < nrows * w; e += blockDim.x) {
-    const int r = e / w;
-    const int c = e - r * w;
-    A[(long long)(base + r) * lda + j0 + c] = tile[c * R + r];
-  }
-}
-
-template <typename T>
-int launch_panel_leaf(int m, int j0, int w, T* A, long long lda, int32_t* ipiv, int32_t* info,
-                      int info_base, void* slots, unsigned* barrier, hipStream_t s) {
-  (void)info_base;
-  const int rows = m - j0;
-  if (rows <= 0 || w <= 0) return LP_OK;
-  if (w > kLeafMax) return LP_ENOTSUP;
-  const int ncu = num_cus();
-  int R = (int)cdiv(rows, ncu);
-  R = (int)(cdiv(R, 64) * 64);
-  if (R < 256) R = 256;
-  const int G = (int)cdiv(rows, R);
-  const size_t lds = sizeof(T) * (size_t)R * w;
-  if (lds > 160 * 1024 - 2048) return LP_ENOTSUP;
-  if (G > ncu || G > 256) return LP_ENOTSUP;
-  hipLaunchKernelGGL((panel_leaf_kernel<T>), dim3(G), dim3(256), lds, s, m, j0, w, A, lda, ipiv,
-                     info, R, G, (char*)slots, barrier);
-  LP_LAUNCH_CHECK();
-  return LP_OK;
-}
-
-template int launch_panel_leaf<double>(int, int, int, double*, long long, int32_t*, int32_t*,
-                                       int, void*, unsigned*, hipStream_t);
-template int launch_panel_leaf<float>(int, int, int, float*, long long, int32_t*, int32_t*, int,
-                                      void*, unsigned*, hipStream_t);
 
 // ------------------------------------------------------- row interchanges
 // The interchanges of steps k1..k2-1 (row j <-> row ipiv[j] >= j, in order)
@@ -485,29 +187,6 @@ template int launch_swap_apply<float>(float*, long long, int, int, int, int, int
 //   FP64 16x16x4: output (lane l, reg v) = D[l/16 + 4v][l%16]; step t uses k = l/16 + 4t
 //   FP32 16x16x4: output (lane l, reg v) = D[4(l/16) + v][l%16]; step t uses k = 4(l/16) + t
 // (A operand: lane l supplies row l % 16 at that k; layouts checked on the device.)
-template <typename T>
-struct Mfma16;
-
-template <>
-struct Mfma16<double> {
-  typedef d4 acc;
-  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int g, int v) { return g + 4 * v; }
-  static __device__ __forceinline__ int kidx(int g, int t) { return g + 4 * t; }
-};
-
-template <>
-struct Mfma16<float> {
-  typedef f4 acc;
-  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int g, int v) { return 4 * g + v; }
-  static __device__ __forceinline__ int kidx(int g, int t) { return 4 * g + t; }
-};
-
 // Inverse of each 16 x 16 unit lower diagonal block of L (rows beyond m are
 // treated as identity).  Linv[r] is stored row-major, 256 entries per block.
 template <typename T>

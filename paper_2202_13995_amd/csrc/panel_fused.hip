@@ -1,0 +1,521 @@
+// One-launch panel factorization.
+//
+// Paper, section "High Performance Linpack", "Base Implementation": each
+// iteration first decomposes the diagonal block (the LU kernel) and updates the
+// blocks below it (the left blocks).  With partial pivoting these form one tall
+// column panel, factored here by a single persistent launch so that, while the
+// previous iteration's inner-block multiplication occupies the GPU, the panel
+// waits for compute units once instead of once per sub-step.
+//
+// G workgroups (at most one per compute unit, all resident) split the panel's
+// rows [c0, m) into consecutive blocks of R rows (R a multiple of 32).  The
+// panel's W columns are processed right-looking in leaves of 32 columns:
+//   (A) each workgroup loads its rows of the leaf into LDS (column-major);
+//   (B) per column: every workgroup publishes its best candidate (largest |a|,
+//       lowest row on ties, NaN below every number), all meet at a grid
+//       barrier, every workgroup picks the same winner, exchanges the pivot
+//       and diagonal rows inside the leaf, scales by the pivot (division) and
+//       applies the rank-1 update to the rest of the leaf;
+//   (C) the factored leaf is written back;
+//   (D) the leaf's row exchanges are applied to the panel's other columns:
+//       each workgroup copies, for every destination row it owns, the source
+//       row to a staging buffer; grid barrier; then copies staging to the
+//       destination (the net permutation of the leaf's swaps comes from the
+//       same parallel plan as the full-matrix exchanges);
+//   (E) the workgroup owning the leaf's rows solves them against the leaf's
+//       unit lower triangle (the "top" update inside the panel); grid barrier;
+//   (F) every workgroup subtracts L(own rows, leaf) * U(leaf rows, right of the
+//       leaf) from its rows below the leaf on the matrix cores.
+// All data one workgroup writes and another reads moves through relaxed
+// agent-scope atomics (L2-coherent accesses), so no fence ever writes back or
+// invalidates the L2 (see grid_barrier).
+#include <climits>
+#include <type_traits>
+
+#include "common.h"
+#include "device.h"
+#include "swap_plan.h"
+
+namespace lp {
+namespace {
+
+constexpr int kLW = 32;          // leaf width
+constexpr int kMaxEnt = 2 * kLW;  // gather entries of one leaf's exchanges
+constexpr int kMaxG = 256;        // workgroups per panel launch
+constexpr int kKeySlots = 1024 * kMaxG;  // one key per (column, workgroup)
+
+// Calls f(std::integral_constant<int, J>) for J = J0 .. N-1 in order while it
+// returns true; the index is a compile-time constant inside f.
+template <int J, int N, typename F>
+__device__ __forceinline__ bool static_for(F& f) {
+  if constexpr (J < N) {
+    if (!f(std::integral_constant<int, J>{})) return false;
+    return static_for<J + 1, N>(f);
+  } else {
+    return true;
+  }
+}
+
+__device__ __forceinline__ void wg_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
+    int m, int c0, int W, T* __restrict__ A, long long lda, int32_t* __restrict__ ipiv,
+    int32_t* __restrict__ info, int R, int G, char* __restrict__ slots,
+    unsigned* __restrict__ barrier, T* __restrict__ staging,
+    unsigned long long* __restrict__ keys, unsigned long long* __restrict__ keys_next) {
+  typedef Mfma16<T> MF;
+  typedef typename MF::acc acc_t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);  // [kLW][R] column-major
+  __shared__ double red_key[2][4];
+  __shared__ int red_idx[2][4];
+  __shared__ T wrow[2][4][kLW];  // each wave's candidate row, by column parity
+  __shared__ T drw[2][kLW];      // the diagonal row, by column parity
+  __shared__ T prow[kLW];
+  __shared__ T drow[kLW];
+  __shared__ int s_p;
+  __shared__ int s_flag;
+  __shared__ int s_piv[kLW];
+  __shared__ int pl_nxt[kLW];
+  __shared__ int pl_B[kLW];
+  __shared__ int pl_flag[2 * kLW];
+  __shared__ int pl_dst[kMaxEnt];
+  __shared__ int pl_src[kMaxEnt];
+  __shared__ int pl_n;
+  __shared__ unsigned long long red_enc[4];
+  __shared__ int red_g[4];
+  __shared__ int s_timeout;
+
+  const LeafLayout lay = leaf_layout<T>(G);
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int base = c0 + g * R;
+  const int nrows = min(R, m - base);
+  unsigned nbar = 0;
+  // the first zero pivot so far (read once; only this launch writes it meanwhile)
+  int info_val = (g == 0 && tid == 0) ? *info : 0;
+  // the next panel launch on this stream has at most W columns and G workgroups
+  if (G > 1) {
+    for (int e = g * blockDim.x + tid; e < W * G; e += G * blockDim.x)
+      xstore(&keys_next[(size_t)(e / G) * kMaxG + (e % G)], 0ull);
+  }
+  if (tid == 0) s_timeout = 0;
+
+  // every workgroup executes the same sequence of these
+  auto sync_all = [&]() -> bool {
+    if (G == 1) {
+      wg_sync();
+      return true;
+    }
+    const bool ok = grid_barrier(barrier, (unsigned)G * (nbar + 1u), &s_flag);
+    ++nbar;
+    return ok;
+  };
+
+  const int nleaf = (W + kLW - 1) / kLW;
+  for (int b = 0; b < nleaf; ++b) {
+    const int cb = c0 + b * kLW;
+    const int wb = min(kLW, c0 + W - cb);
+    const int right0 = cb + wb;
+    const int nright = c0 + W - right0;
+    const int rlo = max(cb - base, 0);
+
+    // (A) the leaf's rows >= cb: coalesced loads into LDS, then each thread
+    // takes its rows into registers
+    for (int e = rlo * wb + tid; e < nrows * wb; e += blockDim.x) {
+      const int r = e / wb;
+      const int c = e - r * wb;
+      tile[c * R + r] = xload(&A[(long long)(base + r) * lda + cb + c]);
+    }
+    __syncthreads();
+    T x[RPT][kLW];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + 256 * q;
+      const bool act = r >= rlo && r < nrows;
+#pragma unroll
+      for (int c = 0; c < kLW; ++c) x[q][c] = (act && c < wb) ? tile[c * R + r] : T(0);
+    }
+
+    // (B) the leaf's columns; the column index is a compile-time constant in
+    // every step so that the rows stay in registers
+    auto column = [&](auto jc) -> bool {
+      constexpr int jj = decltype(jc)::value;
+      if (jj < wb) {
+        const int dg = cb + jj;
+        const int par = jj & 1;
+        double bk = -2.0;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = tid + 256 * q;
+          const int gi = base + r;
+          if (r < nrows && gi >= dg) {
+            const T v = x[q][jj];
+            const double k = (v != v) ? -1.0 : fabs((double)v);
+            if (better(k, gi, bk, bi)) {
+              bk = k;
+              bi = gi;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ok = __shfl_xor(bk, off);
+          const int oi = __shfl_xor(bi, off);
+          if (better(ok, oi, bk, bi)) {
+            bk = ok;
+            bi = oi;
+          }
+        }
+        // the wave's candidate row and the diagonal row go to LDS
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int gi = base + tid + 256 * q;
+          if (bi != INT_MAX && gi == bi) {
+#pragma unroll
+            for (int c = 0; c < kLW; ++c) wrow[par][wave][c] = x[q][c];
+          }
+          if (gi == dg && tid + 256 * q < nrows) {
+#pragma unroll
+            for (int c = 0; c < kLW; ++c) drw[par][c] = x[q][c];
+          }
+        }
+        if (lane == 0) {
+          red_key[par][wave] = bk;
+          red_idx[par][wave] = bi;
+        }
+        __syncthreads();
+        int wbest = 0;
+        bk = red_key[par][0];
+        bi = red_idx[par][0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+          if (better(red_key[par][t], red_idx[par][t], bk, bi)) {
+            bk = red_key[par][t];
+            bi = red_idx[par][t];
+            wbest = t;
+          }
+        const bool own_diag = dg >= base && dg < base + nrows;
+        int p;
+        const T* urow;  // the pivot row (LDS)
+        const T* drv;   // the old diagonal row (LDS)
+        if (G == 1) {
+          const T dv = drw[par][jj];
+          p = (dv != dv) ? dg : bi;
+          drv = drw[par];
+          urow = (p == dg) ? drv : wrow[par][wbest];
+        } else {
+          // publish the row data, then the key: a non-zero key means "my slot
+          // for this column is complete"
+          char* sb = slots + (size_t)par * lay.buf_bytes;
+          int* sidx = reinterpret_cast<int*>(sb + lay.idx_off);
+          T* srows = reinterpret_cast<T*>(sb + lay.rows_off);
+          T* sdiag = reinterpret_cast<T*>(sb + lay.diag_off);
+          int* sflag = reinterpret_cast<int*>(sb + lay.flag_off);
+          unsigned long long* ckeys = keys + (size_t)(dg - c0) * kMaxG;
+          if (tid == 0) xstore(&sidx[g], bi);
+          if (tid < wb && bi != INT_MAX) xstore(&srows[(size_t)g * kLeafMax + tid], wrow[par][wbest][tid]);
+          if (own_diag) {
+            if (tid < wb) xstore(&sdiag[tid], drw[par][tid]);
+            if (tid == 64) {
+              const T dv = drw[par][jj];
+              xstore(sflag, (dv != dv) ? 1 : 0);
+            }
+          }
+          wg_sync();
+          if (tid == 0) {
+            unsigned long long ek = 1ull;  // no candidate
+            if (bi != INT_MAX)
+              ek = (bk < 0.0) ? 2ull : 3ull + (unsigned long long)__double_as_longlong(bk);
+            xstore(&ckeys[g], ek);
+          }
+          // wait for every workgroup's key; the largest wins, the lowest
+          // workgroup (hence the lowest row) on ties
+          unsigned long long kv = 0ull;
+          int kg = INT_MAX;
+          if (tid < G) {
+            const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+            while ((kv = xload(&ckeys[tid])) == 0ull) {
+              __builtin_amdgcn_s_sleep(1);
+              if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
+                s_timeout = 1;
+                break;
+              }
+            }
+            kg = tid;
+          }
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long ov = __shfl_xor(kv, off);
+            const int og = __shfl_xor(kg, off);
+            if (ov > kv || (ov == kv && og < kg)) {
+              kv = ov;
+              kg = og;
+            }
+          }
+          if (lane == 0) {
+            red_enc[wave] = kv;
+            red_g[wave] = kg;
+          }
+          __syncthreads();
+          if (s_timeout) {
+            if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
+            return false;
+          }
+          kv = red_enc[0];
+          kg = red_g[0];
+#pragma unroll
+          for (int t = 1; t < 4; ++t)
+            if (red_enc[t] > kv || (red_enc[t] == kv && red_g[t] < kg)) {
+              kv = red_enc[t];
+              kg = red_g[t];
+            }
+          // one round trip: winner's row and index, diagonal row, NaN flag
+          if (tid < wb) {
+            prow[tid] = xload(&srows[(size_t)kg * kLeafMax + tid]);
+            drow[tid] = xload(&sdiag[tid]);
+          }
+          if (tid == 64) {
+            const int pw = xload(&sidx[kg]);
+            s_p = xload(sflag) ? dg : pw;
+          }
+          __syncthreads();
+          p = s_p;
+          drv = drow;
+          urow = (p == dg) ? drv : prow;
+        }
+        const T piv = urow[jj];
+        if (tid == 0) s_piv[jj] = p;
+        if (g == 0 && tid == 0) {
+          ipiv[dg] = p;
+          if (piv == T(0) && info_val == 0) {
+            info_val = dg + 1;
+            *info = info_val;
+          }
+        }
+        // exchange rows dg and p, then scale and update the rows below
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = tid + 256 * q;
+          const int gi = base + r;
+          if (p != dg && r < nrows) {
+            if (gi == p) {
+#pragma unroll
+              for (int c = 0; c < kLW; ++c) x[q][c] = drv[c];
+            } else if (gi == dg) {
+#pragma unroll
+              for (int c = 0; c < kLW; ++c) x[q][c] = urow[c];
+            }
+          }
+          if (piv != T(0) && r < nrows && gi > dg) {
+            const T l = x[q][jj] / piv;
+            x[q][jj] = l;
+#pragma unroll
+            for (int c = jj + 1; c < kLW; ++c) x[q][c] -= l * urow[c];
+          }
+        }
+        if (G > 1) __syncthreads();  // prow/drow/s_p are reused by the next column
+      }
+      return true;
+    };
+    if (!static_for<0, kLW>(column)) return;
+
+    // (C) the factored leaf to LDS (kept for the solve and the update), then
+    // coalesced stores to memory
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + 256 * q;
+      if (r >= rlo && r < nrows) {
+#pragma unroll
+        for (int c = 0; c < kLW; ++c)
+          if (c < wb) tile[c * R + r] = x[q][c];
+      }
+    }
+    __syncthreads();
+    for (int e = rlo * wb + tid; e < nrows * wb; e += blockDim.x) {
+      const int r = e / wb;
+      const int c = e - r * wb;
+      xstore(&A[(long long)(base + r) * lda + cb + c], tile[c * R + r]);
+    }
+
+    // (D) the leaf's exchanges on the panel's other columns
+    build_swap_plan(s_piv, cb, cb + wb, pl_nxt, pl_B, nullptr, pl_flag, pl_dst, pl_src, &pl_n);
+    __syncthreads();
+    const int nent = pl_n;
+    const int nout = W - wb;
+    const int nleft = cb - c0;
+    if (nout > 0 && nent > 0) {
+      for (int e2 = tid; e2 < nent * nout; e2 += blockDim.x) {
+        const int e = e2 / nout;
+        const int ci = e2 - e * nout;
+        const int d = pl_dst[e];
+        if ((d - c0) / R == g) {
+          const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
+          xstore(&staging[(long long)e * W + ci], xload(&A[(long long)pl_src[e] * lda + col]));
+        }
+      }
+      if (!sync_all()) {
+        if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
+        return;
+      }
+      for (int e2 = tid; e2 < nent * nout; e2 += blockDim.x) {
+        const int e = e2 / nout;
+        const int ci = e2 - e * nout;
+        const int d = pl_dst[e];
+        if ((d - c0) / R == g) {
+          const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
+          xstore(&A[(long long)d * lda + col], xload(&staging[(long long)e * W + ci]));
+        }
+      }
+    }
+    if (nright <= 0) {
+      wg_sync();
+      continue;
+    }
+
+    // (E) the leaf's rows right of the leaf: U = L_bb^-1 * A(leaf rows, right)
+    if ((cb - c0) / R == g) {
+      wg_sync();
+      const int lr = cb - base;
+      for (int col = tid; col < nright; col += blockDim.x) {
+        T x[kLW];
+#pragma unroll
+        for (int i = 0; i < kLW; ++i)
+          x[i] = (i < wb) ? xload(&A[(long long)(cb + i) * lda + right0 + col]) : T(0);
+#pragma unroll
+        for (int i = 1; i < kLW; ++i) {
+          if (i < wb) {
+            T acc = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc -= tile[k * R + lr + i] * x[k];
+            x[i] = acc;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kLW; ++i)
+          if (i < wb) xstore(&A[(long long)(cb + i) * lda + right0 + col], x[i]);
+      }
+    }
+    if (!sync_all()) {
+      if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
+      return;
+    }
+
+    // (F) own rows below the leaf: A(r, right) -= L(r, leaf) * U(leaf, right)
+    const int r_first = max(right0 - base, 0);
+    if (r_first < nrows) {
+      const int gq = lane >> 4;
+      const int l16 = lane & 15;
+      const int rb0 = r_first & ~15;
+      const int nrb = (nrows - rb0 + 15) >> 4;
+      const int ncb = (nright + 15) >> 4;
+      for (int cbk = wave; cbk < ncb; cbk += 4) {
+        const int col = right0 + 16 * cbk + l16;
+        const bool colok = col < c0 + W;
+        T bfr[2][4];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int k = 16 * s2 + MF::kidx(gq, t);
+            bfr[s2][t] = (k < wb && colok) ? xload(&A[(long long)(cb + k) * lda + col]) : T(0);
+          }
+        for (int rg = 0; rg < nrb; rg += 4) {
+          acc_t acc[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int rloc = rb0 + 16 * (rg + u);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = rloc + MF::drow(gq, v);
+              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
+              acc[u][v] = ok ? -xload(&A[(long long)(base + row) * lda + col]) : T(0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int row = rb0 + 16 * (rg + u) + l16;
+            const bool rowok = (rg + u < nrb) && row < nrows;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const int k = 16 * s2 + MF::kidx(gq, t);
+                const T a = (rowok && k < wb) ? tile[k * R + row] : T(0);
+                acc[u] = MF::mma(a, bfr[s2][t], acc[u]);
+              }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int rloc = rb0 + 16 * (rg + u);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = rloc + MF::drow(gq, v);
+              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
+              if (ok) xstore(&A[(long long)(base + row) * lda + col], -acc[u][v]);
+            }
+          }
+        }
+      }
+    }
+    wg_sync();
+  }
+}
+
+}  // namespace
+
+size_t panel_staging_bytes(int W) { return sizeof(double) * (size_t)kMaxEnt * (size_t)W; }
+size_t panel_keys_bytes() { return sizeof(unsigned long long) * (size_t)kKeySlots; }
+
+template <typename T>
+int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
+                       void* slots, unsigned* barrier, void* staging, void* keys,
+                       void* keys_next, hipStream_t s) {
+  const int rows = m - c0;
+  if (rows <= 0 || W <= 0) return LP_OK;
+  if (W > rows) return LP_ENOTSUP;
+  const int ncu = num_cus();
+  int R, G;
+  constexpr int kRowsMax = (sizeof(T) == 8) ? 512 : 1024;  // 128 KB of LDS for the leaf
+  if (rows <= kRowsMax) {
+    R = (rows + 31) & ~31;
+    G = 1;
+  } else {
+    R = (int)cdiv(rows, std::min(ncu, 256));
+    R = (R + 31) & ~31;
+    if (R < 256) R = 256;
+    G = (int)cdiv(rows, R);
+  }
+  if (R > kRowsMax || G > ncu || G > kMaxG || W > 1024) return LP_ENOTSUP;
+  const size_t lds = sizeof(T) * (size_t)R * kLW;
+  if (R <= 256)
+    hipLaunchKernelGGL((panel_fused_kernel<T, 1>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
+                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
+                       (unsigned long long*)keys, (unsigned long long*)keys_next);
+  else if (R <= 512)
+    hipLaunchKernelGGL((panel_fused_kernel<T, 2>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
+                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
+                       (unsigned long long*)keys, (unsigned long long*)keys_next);
+  else if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((panel_fused_kernel<T, 4>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
+                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
+                       (unsigned long long*)keys, (unsigned long long*)keys_next);
+  else
+    return LP_ENOTSUP;
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template int launch_panel_fused<double>(int, int, int, double*, long long, int32_t*, int32_t*,
+                                        void*, unsigned*, void*, void*, void*, hipStream_t);
+template int launch_panel_fused<float>(int, int, int, float*, long long, int32_t*, int32_t*,
+                                       void*, unsigned*, void*, void*, void*, hipStream_t);
+
+}  // namespace lp

@@ -179,6 +179,13 @@ int lu_solve_ir(int n, int nb, int prec, const double *A, int lda, const double 
                 int ldb, double *X, int ldx, int nrhs, int max_iter, void *work,
                 size_t work_bytes, lp_ir_report *rep, void *stream);
 
+/* Refinement decision used by lu_solve_ir, from the scaled-residual history
+ * h[0..len) (h[0] after x0, h[k] after the k-th correction): returns 1 when the
+ * last value is below 16 (converged), 2 to give up (last value not finite, the
+ * last two steps both grew, or corrections == max_iter), 0 to refine again.
+ * Host-only, pure. */
+int lp_ir_decide(const double *h, int len, int corrections, int max_iter);
+
 /* --------------------------------------------- building blocks (exported) */
 /* The steps of one block column, callable on their own (used by the tests
  * and by callers that schedule the steps themselves).  Same conventions. */

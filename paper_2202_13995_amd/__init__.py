@@ -78,6 +78,7 @@ SIGNATURES = {
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
     "lu_solve_ir": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ,
                          ctypes.POINTER(IRReport), _VP]),
+    "lp_ir_decide": (_I, [ctypes.POINTER(ctypes.c_double), _I, _I, _I]),
     "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lp_laswp_workspace_bytes": (_SZ, [_I]),
     "lp_laswp": (_I, [_I, _VP, _I, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
@@ -236,6 +237,12 @@ def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: i
                                           X.data_ptr(), ldx, nrhs, max_iter, work.data_ptr(),
                                           work.numel(), ctypes.byref(rep), _stream(stream)))
     return X, rep
+
+
+def ir_decide(history, corrections: int, max_iter: int) -> int:
+    """The refinement rule of lu_solve_ir (host-only): 0 refine, 1 converged, 2 give up."""
+    arr = (ctypes.c_double * max(1, len(history)))(*history)
+    return int(_lib().lp_ir_decide(arr, len(history), corrections, max_iter))
 
 
 # ------------------------------------------------------------ building blocks

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/lp.h"
 
 #define LP_HIP_TRY(expr)                              \
@@ -43,6 +45,10 @@ int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long l
                        const void* B, long long ldb, void* C, long long ldc, hipStream_t s,
                        int kind = kGemmTrailing);
 
+// binary32 storage: C := C - A B with operands on FP32, BF16 or FP16 MFMA.
+int launch_gemm_update_lp(int prec, int M, int N, int K, const float* A, long long lda,
+                          const float* B, long long ldb, float* C, long long ldc, hipStream_t s);
+
 // B := L^-1 B, L unit lower m x m (m <= 512); work: trsm_workspace_bytes(m).
 size_t trsm_workspace_bytes(int m);
 template <typename T>
@@ -71,6 +77,14 @@ template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
                        void* keys_next, hipStream_t s);
+
+// Factorization / solve / residual (driver.hip, solve.hip), used by the IR driver.
+template <typename T>
+int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, const int32_t* info,
+                    T* B, long long ldb, int nrhs, int32_t* status, hipStream_t s);
+int launch_residual(int n, const double* A, long long lda, const double* X, long long ldx,
+                    const double* B, long long ldb, int nrhs, double* out, hipStream_t s,
+                    double* Rv, long long ldr);
 
 // Zero a range of 32-bit words (a kernel, not a memset node).
 int launch_zero_words(void* p, size_t nwords, hipStream_t s);

@@ -29,11 +29,6 @@
 
 namespace lp {
 
-template <typename T>
-int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, const int32_t* info,
-                    T* B, long long ldb, int nrhs, int32_t* status, hipStream_t s);
-int launch_residual(int n, const double* A, long long lda, const double* X, long long ldx,
-                    const double* B, long long ldb, int nrhs, double* out, hipStream_t s);
 
 int num_cus() {
   static std::atomic<int> cache[64];
@@ -380,7 +375,7 @@ int residual_check(int n, const double* A, int lda, const double* X, int ldx, co
   if (ldb < std::max(1, nrhs)) return -7;
   if (nrhs < 0) return -8;
   if (out == nullptr && nrhs > 0) return -9;
-  return launch_residual(n, A, lda, X, ldx, B, ldb, nrhs, out, (hipStream_t)stream);
+  return launch_residual(n, A, lda, X, ldx, B, ldb, nrhs, out, (hipStream_t)stream, nullptr, 0);
 }
 
 int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
@@ -486,22 +481,6 @@ int lp_convert(int to_f32, int rows, int cols, const void* src, int lds, void* d
   if (dst == nullptr && rows > 0 && cols > 0) return -6;
   if (ldd < std::max(1, cols)) return -7;
   return launch_convert(to_f32, rows, cols, src, lds, dst, ldd, (hipStream_t)stream);
-}
-
-size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs) {
-  (void)n;
-  (void)nb;
-  (void)prec;
-  (void)nrhs;
-  return 0;
-}
-
-int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double* B, int ldb,
-                double* X, int ldx, int nrhs, int max_iter, void* work, size_t work_bytes,
-                lp_ir_report* rep, void* stream) {
-  (void)n; (void)nb; (void)prec; (void)A; (void)lda; (void)B; (void)ldb; (void)X; (void)ldx;
-  (void)nrhs; (void)max_iter; (void)work; (void)work_bytes; (void)rep; (void)stream;
-  return LP_ENOTSUP;
 }
 
 }  // extern "C"

@@ -196,7 +196,8 @@ int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long l
     LP_LAUNCH_CHECK();
     return LP_OK;
   }
-  return LP_ENOTSUP;
+  return launch_gemm_update_lp(prec, M, N, K, (const float*)A, lda, (const float*)B, ldb,
+                               (float*)C, ldc, s);
 }
 
 }  // namespace lp

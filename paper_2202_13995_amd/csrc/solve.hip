@@ -161,7 +161,9 @@ __global__ __launch_bounds__(256) void residual_rows_kernel(int n, const double*
                                                             const double* __restrict__ B,
                                                             long long ldb, int nrhs, int c0,
                                                             int with_anorm,
-                                                            unsigned long long* __restrict__ tmp) {
+                                                            unsigned long long* __restrict__ tmp,
+                                                            double* __restrict__ Rv,
+                                                            long long ldr) {
   __shared__ double red[4][kRhsChunk + 1];
   const int i = blockIdx.x;
   const int cw = min(kRhsChunk, nrhs - c0);
@@ -197,6 +199,7 @@ __global__ __launch_bounds__(256) void residual_rows_kernel(int n, const double*
     for (int c = 0; c < cw; ++c) {
       const double ax = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
       const double r = ax - B[(long long)i * ldb + c0 + c];
+      if (Rv != nullptr) Rv[(long long)i * ldr + c0 + c] = -r;
       atomic_max_nonneg(&tmp[1 + c0 + c], r);
       atomic_max_nonneg(&tmp[1 + nrhs + c0 + c], X[(long long)i * ldx + c0 + c]);
       atomic_max_nonneg(&tmp[1 + 2 * nrhs + c0 + c], B[(long long)i * ldb + c0 + c]);
@@ -284,8 +287,10 @@ template int launch_lu_solve<double>(int, const double*, long long, const int32_
 template int launch_lu_solve<float>(int, const float*, long long, const int32_t*, const int32_t*,
                                     float*, long long, int, int32_t*, hipStream_t);
 
+// Rv (optional): also writes r = B - A X (n x nrhs, ld ldr).
 int launch_residual(int n, const double* A, long long lda, const double* X, long long ldx,
-                    const double* B, long long ldb, int nrhs, double* out, hipStream_t s) {
+                    const double* B, long long ldb, int nrhs, double* out, hipStream_t s,
+                    double* Rv, long long ldr) {
   if (nrhs <= 0) return LP_OK;
   for (int g0 = 0; g0 < nrhs; g0 += 64) {
     const int gw = min(64, nrhs - g0);
@@ -295,7 +300,8 @@ int launch_residual(int n, const double* A, long long lda, const double* X, long
       for (int c0 = 0; c0 < gw; c0 += kRhsChunk) {
         hipLaunchKernelGGL(residual_rows_kernel, dim3(n), dim3(256), 0, s, n, A, lda, X + g0, ldx,
                            B + g0, ldb, gw, c0, c0 == 0 ? 1 : 0,
-                           reinterpret_cast<unsigned long long*>(out + 5 * g0));
+                           reinterpret_cast<unsigned long long*>(out + 5 * g0),
+                           Rv == nullptr ? nullptr : Rv + g0, ldr);
         LP_LAUNCH_CHECK();
       }
     }

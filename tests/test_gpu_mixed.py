@@ -1,0 +1,139 @@
+"""GPU parity for the low-precision factorization and iterative refinement.
+
+The binary32 trailing update is checked element-wise against binary64 products
+of the same rounded operands (bfloat16 / half rounding from the reference in
+oracle/ir.py), the binary32 factorization against the oracle's factorization of
+the same binary32 matrix, and the refined solution against the binary64
+oracle's solution (scaled residual < 16 and the forward error bound).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import ir
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2202_13995_amd as lp
+    return lp
+
+
+def cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (1, 1, 1), (130, 70, 33), (300, 257, 64),
+                                   (1000, 1000, 256), (2050, 130, 512)])
+def test_gemm_update_low_precision(lp, prec, M, N, K):
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = rng.uniform(-1, 1, (M, K)).astype(np.float32)
+    B = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+    C = rng.uniform(-1, 1, (M, N)).astype(np.float32)
+    tC = cuda(C)
+    lp.gemm_update(tC, cuda(A), cuda(B), prec=prec)
+    Ar = ir.round_to(A, prec).astype(np.float64)
+    Br = ir.round_to(B, prec).astype(np.float64)
+    ref = C.astype(np.float64) - Ar @ Br
+    bound = (K + 2) * U32 * (np.abs(C) + np.abs(Ar) @ np.abs(Br)) + 1e-30
+    err = np.abs(host(tC).astype(np.float64) - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+@pytest.mark.parametrize("n,nb", [(64, 32), (300, 64), (1000, 128), (2048, 256)])
+def test_fp32_factorization_matches_oracle_on_fp32_matrix(lp, n, nb):
+    a32 = inputs.matrix(40 + n, n).astype(np.float32)
+    tA = cuda(a32)
+    ipiv, info = lp.lu_factor(tA, nb, "fp32")
+    lu_o, piv_o, info_o = oracle.getrf(a32.astype(np.float64))
+    assert int(host(info)[0]) == info_o == 0
+    got_piv = host(ipiv)[:n]
+    agree = np.mean(got_piv == piv_o)
+    assert agree >= 0.99, agree          # binary32 near-ties may legitimately differ
+    if agree == 1.0:
+        assert np.max(np.abs(host(tA) - lu_o)) <= 200 * n * U32
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_refinement_shifted_matrix(lp, prec):
+    import torch
+    n, nb = 1024, 128
+    A = inputs.matrix(2202, n, shift=float(n))
+    B = inputs.rhs(2202, n, 2)
+    tA, tB = cuda(A), cuda(B)
+    X, rep = lp.solve_ir(tA, tB, nb, prec)
+    r = rep.as_dict()
+    assert r["converged"] == 1 and r["fell_back"] == 0, r
+    assert r["scaled_residual"] < 16 and r["iterations"] <= 6, r
+    x = host(X)
+    x_o = oracle.solve(A, B)
+    # refinement stops at scaled residual < 16, which bounds the forward error by
+    # ~cond * 16 * n * eps; the stated tolerance is 1e-10
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    res = oracle.residual(A, x, B)
+    assert np.all(res[:, 0] < 16)
+    # inputs untouched
+    assert np.array_equal(host(tA), A) and np.array_equal(host(tB), B)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_refinement_unshifted_matrix(lp, prec):
+    n, nb = 1000, 64
+    A = inputs.matrix(77, n)
+    B = inputs.rhs(77, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, prec)
+    r = rep.as_dict()
+    assert r["scaled_residual"] < 16, r
+    x = host(X)
+    x_o = oracle.solve(A, B)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    if prec == "fp32":
+        assert r["converged"] == 1 and r["fell_back"] == 0 and r["iterations"] <= 4, r
+
+
+def test_refinement_fallback_recorded(lp):
+    # max_iter = 0 forbids corrections: unless x0 already passes, the FP64 path runs
+    n = 512
+    A = inputs.matrix(9, n)
+    B = inputs.rhs(9, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), 64, "bf16", max_iter=0)
+    r = rep.as_dict()
+    assert r["fell_back"] == 1 and r["converged"] == 1, r
+    x_o = oracle.solve(A, B)
+    assert np.max(np.abs(host(X) - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+
+
+def test_refinement_singular_low_precision_falls_back_and_reports(lp):
+    n = 256
+    A = inputs.matrix(5, n)
+    A[:, 10] = 0.0
+    B = inputs.rhs(5, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), 64, "fp32")
+    r = rep.as_dict()
+    assert r["info"] == 11 and r["fell_back"] == 1 and r["fallback_info"] == 11
+    assert r["converged"] == 0
+
+
+def test_fp64_through_refinement_entry(lp):
+    n = 300
+    A = inputs.matrix(12, n)
+    B = inputs.rhs(12, n, 3)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), 64, "fp64")
+    r = rep.as_dict()
+    assert r["converged"] == 1 and r["fell_back"] == 0 and r["iterations"] == 0
+    x_o = oracle.solve(A, B)
+    assert np.max(np.abs(host(X) - x_o)) / np.max(np.abs(x_o)) <= 1e-10

@@ -1,0 +1,79 @@
+"""Refinement host logic (no GPU): the library's decision rule against the
+reference rule, and the reference loop against what mixed-precision
+refinement must achieve."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import ir
+
+
+def lib_decide(history, corrections, max_iter):
+    import paper_2202_13995_amd as lp
+    return lp.ir_decide(history, corrections, max_iter)
+
+
+CASES = [
+    ([0.5], 0, 30),
+    ([40.0], 0, 30),
+    ([40.0, 20.0], 1, 30),
+    ([40.0, 20.0, 15.9], 2, 30),
+    ([40.0, 50.0], 1, 30),
+    ([40.0, 50.0, 60.0], 2, 30),
+    ([40.0, 30.0, 50.0, 60.0], 3, 30),
+    ([40.0, 30.0, 35.0, 32.0], 3, 30),
+    ([float("nan")], 0, 30),
+    ([40.0, float("inf")], 1, 30),
+    ([40.0, 39.0, 38.0], 2, 2),
+    ([17.0], 0, 0),
+    ([16.0], 0, 30),
+]
+
+
+@pytest.mark.parametrize("hist,k,mx", CASES)
+def test_decision_rule_matches_reference(hist, k, mx):
+    assert lib_decide(hist, k, mx) == ir.decide(hist, k, mx)
+
+
+def test_decision_rule_values():
+    assert lib_decide([15.99], 0, 30) == 1
+    assert lib_decide([16.0], 0, 30) == 0
+    assert lib_decide([20.0, 30.0, 40.0], 2, 30) == 2
+    assert lib_decide([20.0, 30.0], 1, 30) == 0
+
+
+def test_bf16_rounding_is_nearest_even():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -0.0, 65504.0],
+                 dtype=np.float32)
+    r = ir.round_bf16(x)
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties go to the even mantissa (1.0)
+    assert r[1] == 1.0
+    assert r[2] == np.float32(1.0 + 2 ** -6)
+    assert r[3] == 1.0
+    assert np.signbit(r[4])
+    assert all(np.float32(v).view(np.uint32) & 0xFFFF == 0 for v in r)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_reference_refinement_reaches_fp64_accuracy_shifted(prec):
+    n = 200
+    a = inputs.matrix(31, n, shift=float(n))
+    b = inputs.rhs(31, n, 2)
+    x, hist, ok, k = ir.refine(a, b, prec)
+    assert ok and hist[-1] < 16
+    x_o = oracle.solve(a, b)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-13
+    assert k <= 4
+
+
+def test_reference_refinement_unshifted_fp32():
+    n = 300
+    a = inputs.matrix(32, n)
+    b = inputs.rhs(32, n, 1)
+    x, hist, ok, k = ir.refine(a, b, "fp32")
+    assert ok
+    x_o = oracle.solve(a, b)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10

@@ -186,6 +186,72 @@ int lu_solve_ir(int n, int nb, int prec, const double *A, int lda, const double 
  * Host-only, pure. */
 int lp_ir_decide(const double *h, int len, int corrections, int max_iter);
 
+/* ---------------------------------------------------------------- serving */
+/* A request loop for many independent solves of uneven size (continuous
+ * batching).  Each request is solved as lu_factor + lu_solve (LP_FP64) or as
+ * lu_solve_ir (binary32 factors + binary64 refinement, LP_FP32/BF16/FP16),
+ * and checked with residual_check.  lp_server_create allocates the server's
+ * device memory pool (memory_bytes) once -- the one allocating call of this
+ * library; per-request workspaces come from that pool.  Admission is first
+ * come, first served, by device footprint (lp_request_footprint) and free
+ * launch slots.  Requests with n <= small_n_max run batched: one launch per
+ * batch of up to max_batch requests, one workgroup per request at a time
+ * (batch_workgroups workgroups pull requests from the batch); for those the
+ * low-precision route factors in binary32.  Larger requests run the blocked
+ * path on their own stream (large_slots at once).  Up to batch_slots batches
+ * run concurrently.  A result depends only on the request (size, precision,
+ * data), never on what else was in flight.  Not thread-safe: one thread drives
+ * a server.  The caller keeps A, B and X (device memory) alive until the
+ * request's ticket is returned by lp_server_poll. */
+typedef struct {
+  size_t memory_bytes;  /* device pool size                                     */
+  int small_n_max;      /* n at or below which requests are batched (<= 2048)    */
+  int max_batch;        /* requests per batched launch (<= 4096)                 */
+  int batch_slots;      /* batched launches in flight at once (1..64)            */
+  int batch_workgroups; /* workgroups per batched launch                         */
+  int large_slots;      /* blocked-path requests in flight at once (0..64)       */
+} lp_server_cfg;
+
+typedef struct {
+  const double *A;  /* device, n x n, lda                                        */
+  const double *B;  /* device, n x nrhs, ldb                                     */
+  double *X;        /* device, n x nrhs, ldx: the solution                       */
+  int lda, ldb, ldx;
+  int n, nrhs;      /* 1 <= n <= 131072, 1 <= nrhs <= 64                         */
+  int prec;         /* LP_FP64, or the low-precision route LP_FP32/BF16/FP16     */
+  int nb;           /* panel width for the blocked path                          */
+  int max_iter;     /* refinement limit (0 = 30)                                 */
+} lp_request;
+
+typedef struct {
+  uint64_t ticket;
+  int status;            /* 0 solved; 1 singular or not converged               */
+  int info;              /* first zero pivot + 1 of the factorization used       */
+  int iterations;        /* refinement corrections                               */
+  int fell_back;         /* 1 if the binary64 fallback ran                       */
+  int batched;           /* 1 if it ran in a batched launch                      */
+  double scaled_residual;/* max over right-hand sides                            */
+  double latency_ms;     /* submit -> seen complete by lp_server_poll            */
+} lp_result;
+
+typedef struct lp_server lp_server;
+
+int lp_server_create(const lp_server_cfg *cfg, lp_server **out);
+int lp_server_destroy(lp_server *server);
+/* Queues a request; returns LP_ENOSPC if it could never fit the pool.  Work
+ * already queued on `stream` (NULL: the null stream) when this is called --
+ * typically what produced A and B -- finishes before the request's kernels
+ * read A, B or write X.  X is complete once lp_server_poll has returned the
+ * ticket. */
+int lp_server_submit(lp_server *server, const lp_request *req, uint64_t *ticket, void *stream);
+/* Retires finished work, admits and launches queued requests, and returns up
+ * to cap finished results (host array) in *count. */
+int lp_server_poll(lp_server *server, lp_result *done, int cap, int *count);
+/* Queue length, requests on the device, bytes of the pool in use. */
+int lp_server_pending(const lp_server *server, int *queued, int *running, size_t *pool_used);
+/* Device bytes a request needs from the pool under this configuration. */
+size_t lp_request_footprint(const lp_server_cfg *cfg, const lp_request *req);
+
 /* --------------------------------------------- building blocks (exported) */
 /* The steps of one block column, callable on their own (used by the tests
  * and by callers that schedule the steps themselves).  Same conventions. */

@@ -60,6 +60,29 @@ class FactorProfile(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("memory_bytes", ctypes.c_size_t), ("small_n_max", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("batch_slots", ctypes.c_int),
+                ("batch_workgroups", ctypes.c_int), ("large_slots", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("lda", ctypes.c_int), ("ldb", ctypes.c_int), ("ldx", ctypes.c_int),
+                ("n", ctypes.c_int), ("nrhs", ctypes.c_int), ("prec", ctypes.c_int),
+                ("nb", ctypes.c_int), ("max_iter", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("info", ctypes.c_int),
+                ("iterations", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("batched", ctypes.c_int), ("scaled_residual", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _VP = ctypes.c_void_p
 _I = ctypes.c_int
 _SZ = ctypes.c_size_t
@@ -78,6 +101,14 @@ SIGNATURES = {
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
     "lu_solve_ir": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ,
                          ctypes.POINTER(IRReport), _VP]),
+    "lp_server_create": (_I, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
+    "lp_server_destroy": (_I, [_VP]),
+    "lp_server_submit": (_I, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64),
+                              _VP]),
+    "lp_server_poll": (_I, [_VP, ctypes.POINTER(Result), _I, ctypes.POINTER(ctypes.c_int)]),
+    "lp_server_pending": (_I, [_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_size_t)]),
+    "lp_request_footprint": (_SZ, [ctypes.POINTER(ServerCfg), ctypes.POINTER(Request)]),
     "lp_ir_decide": (_I, [ctypes.POINTER(ctypes.c_double), _I, _I, _I]),
     "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lp_laswp_workspace_bytes": (_SZ, [_I]),
@@ -243,6 +274,92 @@ def ir_decide(history, corrections: int, max_iter: int) -> int:
     """The refinement rule of lu_solve_ir (host-only): 0 refine, 1 converged, 2 give up."""
     arr = (ctypes.c_double * max(1, len(history)))(*history)
     return int(_lib().lp_ir_decide(arr, len(history), corrections, max_iter))
+
+
+class Server:
+    """Continuous-batching solve server (liblp.so's lp_server_*).
+
+    submit() takes device tensors A (n x n), B (n x nrhs) and an output X of the
+    same shape as B, all float64, and returns a ticket; poll() advances the
+    server and returns finished results as dicts.  The tensors of a request are
+    kept alive here until its result has been returned.
+    """
+
+    def __init__(self, memory_bytes: int, small_n_max: int = 512, max_batch: int = 256,
+                 batch_slots: int = 4, batch_workgroups: int = 512, large_slots: int = 4):
+        self.cfg = ServerCfg(memory_bytes, small_n_max, max_batch, batch_slots,
+                             batch_workgroups, large_slots)
+        h = ctypes.c_void_p()
+        _check("lp_server_create", _lib().lp_server_create(ctypes.byref(self.cfg),
+                                                           ctypes.byref(h)))
+        self.h = h
+        self._live = {}
+        self._buf = (Result * 1024)()
+
+    def _request(self, A, B, X, prec, nb, max_iter) -> Request:
+        lda = _mat(A, torch.float64, "A")
+        ldb = _mat(B, torch.float64, "B")
+        ldx = _mat(X, torch.float64, "X")
+        n, nrhs = B.shape
+        return Request(A.data_ptr(), B.data_ptr(), X.data_ptr(), lda, ldb, ldx, n, nrhs,
+                       _prec(prec), nb, max_iter)
+
+    def footprint(self, A, B, X, prec="fp64", nb: int = 64) -> int:
+        req = self._request(A, B, X, prec, nb, 0)
+        return int(_lib().lp_request_footprint(ctypes.byref(self.cfg), ctypes.byref(req)))
+
+    def submit(self, A, B, X, prec="fp64", nb: int = 64, max_iter: int = 0,
+               stream=None) -> int:
+        """Queue a request; it runs after the work already on `stream` (default:
+        torch's current stream) that produced A and B."""
+        req = self._request(A, B, X, prec, nb, max_iter)
+        t = ctypes.c_uint64()
+        _check("lp_server_submit", _lib().lp_server_submit(self.h, ctypes.byref(req),
+                                                           ctypes.byref(t), _stream(stream)))
+        self._live[t.value] = (A, B, X)
+        return t.value
+
+    def poll(self) -> list:
+        cnt = ctypes.c_int()
+        _check("lp_server_poll", _lib().lp_server_poll(self.h, self._buf, len(self._buf),
+                                                       ctypes.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            d = self._buf[i].as_dict()
+            self._live.pop(d["ticket"], None)
+            out.append(d)
+        return out
+
+    def pending(self):
+        q, r, used = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check("lp_server_pending", _lib().lp_server_pending(self.h, ctypes.byref(q),
+                                                             ctypes.byref(r),
+                                                             ctypes.byref(used)))
+        return q.value, r.value, used.value
+
+    def drain(self, timeout_s: float = 120.0) -> list:
+        import time
+        out = []
+        t0 = time.monotonic()
+        while self._live:
+            got = self.poll()
+            out += got
+            if not got:
+                time.sleep(20e-6)
+            if time.monotonic() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+        return out
+
+    def close(self) -> None:
+        if self.h:
+            _lib().lp_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 # ------------------------------------------------------------ building blocks

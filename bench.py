@@ -12,9 +12,16 @@ over the wall time of the K steps (LINPACK's operation count).
 
 The line also carries the roofline of the dominant kernel (the FP64 trailing
 update, bound by the FP64 matrix-core peak), measured with HIP events around
-each of its launches during the timed steps, and the CPU oracle timed on a
-bounded sample on this host.  Rank 0 prints one JSON line on stdout; progress
-goes to stderr.
+each of its launches during the timed steps, its HBM traffic per launch from
+the committed rocprofv3 counter summary (null if the kernel source changed
+since), and the CPU oracle timed on a bounded sample on this host.
+
+Two more objects ride on the same line: `mixed_ir` (the same n solved through
+the low-precision factorization plus binary64 refinement, default bfloat16 on
+A + n I, with the binary64 path timed on that same system for the speedup)
+and `serving` (an open-loop Poisson stream through the continuous-batching
+server: p50/p99 latency and aggregate TFLOP/s).  One process, one GPU; prints
+one JSON line on stdout, progress on stderr.
 """
 from __future__ import annotations
 
@@ -57,6 +64,168 @@ def cpu_baseline(n: int, seed: int) -> dict:
                       f"uniform[-0.5,0.5) seed {seed}; same operation count formula"}
 
 
+PEAK_LOWP_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # dense MFMA peaks
+
+
+def traffic_from_profile(kernel_src: str, n: int, nb: int):
+    """HBM bytes per launch of the trailing update from the committed rocprofv3
+    counter summary, or None when there is none for this workload or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"dgemm_trailing_update_n{n}_nb{nb}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_b):
+        return None
+    src = open(os.path.join(ROOT, "paper_2202_13995_amd", "csrc", kernel_src), "rb").read()
+    if hashlib.sha256(src).hexdigest() != m_sha.group(1):
+        return None
+    return float(m_b.group(1))
+
+
+def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, K, W, nrhs):
+    """K solves of one system through the low-precision factorization plus
+    binary64 refinement (and the binary64 fallback when refinement fails),
+    with the binary64 blocked path timed once on the same system beside it."""
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    inputs.fill_matrix_(A, seed, shift=shift)
+    B = torch.empty((n, nrhs), dtype=torch.float64, device=dev)
+    inputs.fill_rhs_(B, seed)
+    X = torch.empty_like(B)
+    nbytes = lp.lib.lu_solve_ir_workspace_bytes(n, nb, lp.PREC[prec], nrhs)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for w in range(W):
+        lp.solve_ir(A, B, nb, prec, X=X, work=work)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(K):
+        _, rep = lp.solve_ir(A, B, nb, prec, X=X, work=work)
+        reps.append(rep.as_dict())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    del work
+    # binary64 path on the same system, one solve (factor + solve + check)
+    A64 = A.clone()
+    X64 = B.clone()
+    w64 = lp.workspace(n, nb, "fp64", dev)
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lp.lu_factor(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
+    lp.lu_solve(A64, ipiv, info, X64)
+    out = lp.residual_check(A, X64, B)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    s64 = float(out[:, 0].max().item())
+    del A64, X64, w64
+    last = reps[-1]
+    eff = flops(n, nrhs) / dt / 1e12
+    return {
+        "workload": f"{prec.upper()} LU (binary32 panels, {prec} update operands, binary32 "
+                    f"accumulation) + binary64 refinement to scaled residual < 16, n={n}, "
+                    f"nb={nb}, nrhs={nrhs}, A uniform[-0.5,0.5) "
+                    + (f"+ {shift:g} I" if shift else "unshifted") + f", seed {seed}",
+        "prec": prec, "n": n, "nb": nb, "shift": shift,
+        "ms_per_solve": 1e3 * dt,
+        "effective_tflops": eff,
+        "frac_fp64_peak": eff / PEAK_FP64_TFLOPS,
+        "frac_lowp_peak": eff / PEAK_LOWP_TFLOPS[prec],
+        "fp64_ms_same_system": 1e3 * dt64,
+        "fp64_scaled_residual_same_system": s64,
+        "speedup_vs_fp64": dt64 / dt,
+        "iterations": last["iterations"], "converged": last["converged"],
+        "fell_back": last["fell_back"], "scaled_residual": last["scaled_residual"],
+        "history": last["history"],
+        "phase_ms": {k: last[k] for k in ("t_convert_ms", "t_factor_ms", "t_solve0_ms",
+                                          "t_refine_ms", "t_fallback_ms", "t_total_ms")},
+        "residual_pass": bool(last["scaled_residual"] < 16.0),
+    }
+
+
+def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp):
+    """Open-loop Poisson stream of solves through the continuous-batching server.
+
+    Sizes are log-uniform in [64, 4096], 1-8 right-hand sides, half binary64 and
+    half the low-precision route; A uniform[-0.5,0.5).  Inputs are generated on
+    the device before the clock starts; a request is submitted when its arrival
+    time has passed, and its latency runs from its arrival time to the poll that
+    returns it."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(64), np.log(4096), nreq)).astype(int)
+    nrhs = rng.integers(1, 9, nreq)
+    precs = np.where(rng.random(nreq) < 0.5, "fp64", lowp)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    for i in range(nreq):
+        n, r = int(ns[i]), int(nrhs[i])
+        A = torch.empty((n, n), dtype=torch.float64, device=dev)
+        inputs.fill_matrix_(A, seed + 1 + i)
+        B = torch.empty((n, r), dtype=torch.float64, device=dev)
+        inputs.fill_rhs_(B, seed + 1 + i)
+        reqs.append((A, B, torch.empty_like(B), n, r, str(precs[i])))
+    torch.cuda.synchronize()
+
+    def nb_for(n):
+        return 64 if n <= 1024 else 128
+
+    with lp.Server(memory_bytes=int(mem_gib * 2**30), small_n_max=512, max_batch=256,
+                   batch_slots=4, large_slots=8) as sv:
+        # warm-up: one request of each route, untimed
+        for (n, pr) in ((100, "fp64"), (100, lowp), (1500, "fp64"), (1500, lowp)):
+            A = torch.empty((n, n), dtype=torch.float64, device=dev)
+            inputs.fill_matrix_(A, 1)
+            B = torch.empty((n, 1), dtype=torch.float64, device=dev)
+            inputs.fill_rhs_(B, 1)
+            sv.submit(A, B, torch.empty_like(B), prec=pr, nb=nb_for(n))
+        sv.drain()
+        torch.cuda.synchronize()
+        t_arr = {}
+        t_done = {}
+        res = {}
+        i = 0
+        t0 = time.perf_counter()
+        while len(t_done) < nreq:
+            now = time.perf_counter() - t0
+            while i < nreq and arrivals[i] <= now:
+                A, B, X, n, r, pr = reqs[i]
+                t = sv.submit(A, B, X, prec=pr, nb=nb_for(n))
+                t_arr[t] = (i, arrivals[i])
+                i += 1
+            got = sv.poll()
+            now = time.perf_counter() - t0
+            for d in got:
+                t_done[d["ticket"]] = now
+                res[d["ticket"]] = d
+            if not got and i < nreq and arrivals[i] > now + 2e-4:
+                time.sleep(1e-4)
+        t_end = time.perf_counter() - t0
+    lat = np.array([1e3 * (t_done[t] - t_arr[t][1]) for t in t_done])
+    total = sum(flops(q[3], q[4]) for q in reqs)
+    span = t_end - float(arrivals[0])
+    bad = [d for d in res.values() if d["status"] != 0 or not d["scaled_residual"] < 16.0]
+    return {
+        "workload": f"Poisson stream, {nreq} requests at {rate:g}/s offered, n log-uniform "
+                    f"[64,4096], 1-8 rhs, half fp64 / half {lowp}+binary64 refinement, "
+                    f"A uniform[-0.5,0.5), n<=512 batched, pool {mem_gib:g} GiB",
+        "requests": nreq, "offered_rate_per_s": rate,
+        "achieved_rate_per_s": nreq / span,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+        "aggregate_tflops": total / span / 1e12,
+        "makespan_s": span,
+        "batched_fraction": float(np.mean([d["batched"] for d in res.values()])),
+        "fell_back": int(sum(d["fell_back"] for d in res.values())),
+        "failed": len(bad),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +236,18 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2202)
     ap.add_argument("--no-lookahead", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--cpu-n", type=int, default=10240)
+    ap.add_argument("--mixed-prec", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--mixed-n", type=int, default=0, help="default: --n")
+    ap.add_argument("--mixed-nb", type=int, default=0, help="default: --nb")
+    ap.add_argument("--mixed-unshifted", action="store_true",
+                    help="no n*I diagonal shift (refinement may fail and fall back)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-rate", type=float, default=400.0)
+    ap.add_argument("--serve-gib", type=float, default=16.0)
+    ap.add_argument("--serve-lowp", default="fp32", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run a plain element-wise copy-convert of this many MiB of doubles "
@@ -186,9 +366,31 @@ def main() -> int:
         "residual_pass": bool(info_ok and s_max < 16.0),
         "roofline": {"kernel": "dgemm_trailing_update", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic_from_profile("gemm.hip", n, nb),
+                     "algorithmic_bytes_per_launch": sum(p["gemm_bytes"] for p in profs) /
+                     max(gemm_launches, 1)},
         "phases_ms_per_step": phases,
     }
+    del As, Xs
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        mn = args.mixed_n or n
+        mnb = args.mixed_nb or nb
+        shift = 0.0 if args.mixed_unshifted else float(mn)
+        log(f"[bench] mixed {args.mixed_prec} n={mn} nb={mnb} shift={shift:g} ...")
+        line["mixed_ir"] = bench_mixed(lp, inputs, torch, dev, mn, mnb, args.mixed_prec, shift,
+                                       args.seed, K, W, args.nrhs)
+        log(f"[bench] mixed done: {line['mixed_ir']['ms_per_solve']:.1f} ms/solve, "
+            f"speedup {line['mixed_ir']['speedup_vs_fp64']:.2f}x")
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log(f"[bench] serving {args.serve_requests} requests at {args.serve_rate:g}/s ...")
+        line["serving"] = bench_serving(lp, inputs, torch, dev, args.serve_requests,
+                                        args.serve_rate, args.seed, args.serve_gib,
+                                        args.serve_lowp)
+        log(f"[bench] serving done: p50 {line['serving']['p50_ms']:.2f} ms, "
+            f"p99 {line['serving']['p99_ms']:.2f} ms")
     if calib is not None:
         line["calibration"] = calib
     if not args.no_cpu_baseline:

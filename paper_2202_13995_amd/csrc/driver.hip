@@ -54,8 +54,13 @@ constexpr int kMaxNb = 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout of lu_factor (offsets in bytes).
+// Row-exchange plans of consecutive steps live in a ring so that the exchanges
+// left of the panel can run on their own stream, behind the main one.
+constexpr int kPlanRing = 4;
+
 struct FactorLayout {
-  size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, linv_trail, total;
+  size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, plan_bytes, linv_trail,
+      total;
 };
 
 FactorLayout factor_layout(int n, int nb) {
@@ -73,8 +78,9 @@ FactorLayout factor_layout(int n, int nb) {
   off = align_up(off + panel_keys_bytes(), 256);
   L.keys1 = off;
   off = align_up(off + panel_keys_bytes(), 256);
-  L.plan_trail = off;
-  off = align_up(off + swap_plan_bytes(kMaxNb), 256);
+  L.plan_trail = off;  // a ring of kPlanRing plans (see factor_impl)
+  L.plan_bytes = align_up(swap_plan_bytes(kMaxNb), 256);
+  off += kPlanRing * L.plan_bytes;
   L.linv_trail = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
   L.total = off;
@@ -117,7 +123,7 @@ struct Prof {
   struct Span {
     hipEvent_t a, b;
   };
-  std::vector<Span> gemm, panel, swap, trsm;
+  std::vector<Span> gemm, panel, swap, swapl, trsm;
   double gemm_flops = 0, gemm_bytes = 0, swap_bytes = 0, trsm_flops = 0;
 
   int begin(std::vector<Span>& v, hipStream_t s) {
@@ -143,7 +149,7 @@ struct Prof {
     return t;
   }
   void release() {
-    for (auto* v : {&gemm, &panel, &swap, &trsm})
+    for (auto* v : {&gemm, &panel, &swap, &swapl, &trsm})
       for (auto& sp : *v) {
         (void)hipEventDestroy(sp.a);
         (void)hipEventDestroy(sp.b);
@@ -153,11 +159,13 @@ struct Prof {
 
 // RAII holder for the look-ahead stream and its events.
 struct Lookahead {
-  hipStream_t s2 = nullptr;
+  hipStream_t s2 = nullptr;  // the next panel
+  hipStream_t s3 = nullptr;  // row exchanges left of the panel
   std::vector<hipEvent_t> ev;
   ~Lookahead() {
     for (auto e : ev) (void)hipEventDestroy(e);
     if (s2) (void)hipStreamDestroy(s2);
+    if (s3) (void)hipStreamDestroy(s3);
   }
   int event(hipEvent_t* out) {
     hipEvent_t e;
@@ -180,12 +188,17 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   Factor<T> f{n, A, lda, ipiv, info, work + L.slots, (unsigned*)(work + L.barriers),
               (int)L.n_barriers, 0, work + L.staging, {work + L.keys0, work + L.keys1}, s};
   void* linv_trail = work + L.linv_trail;
-  void* plan_trail = work + L.plan_trail;
+  char* plan_ring = work + L.plan_trail;
+  void* plan_trail = plan_ring;  // the current step's plan
   const int npanels = (int)cdiv(n, nb);
   Lookahead la;
   if (lookahead && npanels > 1) {
     LP_HIP_TRY(hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking));
+    LP_HIP_TRY(hipStreamCreateWithFlags(&la.s3, hipStreamNonBlocking));
   }
+  // per ring slot: the left exchanges that read it (s3); the main stream waits
+  // for it before writing the slot again
+  hipEvent_t left_done[kPlanRing] = {nullptr, nullptr, nullptr, nullptr};
   const double es = sizeof(T);
 
   // trailing steps of panel k on stream s over the column range [c0, c1) right of
@@ -227,8 +240,26 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     const int w = std::min(nb, n - j0);
     const int j1 = j0 + w;
     if (panel_done) LP_HIP_TRY(hipStreamWaitEvent(s, panel_done, 0));
+    const int slot = k % kPlanRing;
+    plan_trail = plan_ring + (size_t)slot * L.plan_bytes;
+    if (left_done[slot]) LP_HIP_TRY(hipStreamWaitEvent(s, left_done[slot], 0));
     if (j0 > 0 || j1 < n) {
       if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, s)) != LP_OK) return rc;
+    }
+    if (la.s3 && j0 > 0) {
+      // the exchanges left of the panel: nothing reads those columns before the
+      // final join, so they run behind the main stream
+      hipEvent_t plan_ready;
+      if ((rc = la.event(&plan_ready)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(plan_ready, s));
+      LP_HIP_TRY(hipStreamWaitEvent(la.s3, plan_ready, 0));
+      if ((rc = prof.begin(prof.swapl, la.s3)) != LP_OK) return rc;
+      if ((rc = launch_swap_apply<T>(A, lda, 0, j0, 0, 0, w, plan_trail, la.s3)) != LP_OK)
+        return rc;
+      if ((rc = prof.end(prof.swapl, la.s3)) != LP_OK) return rc;
+      prof.swap_bytes += 2.0 * es * 2.0 * w * j0;
+      if ((rc = la.event(&left_done[slot])) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(left_done[slot], la.s3));
     }
     const bool more = k + 1 < npanels;
     const int w2 = more ? std::min(nb, n - j1) : 0;
@@ -246,9 +277,9 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       f.s = s;
       if ((rc = la.event(&panel_done)) != LP_OK) return rc;
       LP_HIP_TRY(hipEventRecord(panel_done, la.s2));
-      if ((rc = trailing(j0, w, j1 + w2, n, true)) != LP_OK) return rc;
+      if ((rc = trailing(j0, w, j1 + w2, n, la.s3 == nullptr)) != LP_OK) return rc;
     } else {
-      if ((rc = trailing(j0, w, j1, n, true)) != LP_OK) return rc;
+      if ((rc = trailing(j0, w, j1, n, la.s3 == nullptr)) != LP_OK) return rc;
       if (more) {
         if ((rc = prof.begin(prof.panel, s)) != LP_OK) return rc;
         if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
@@ -257,11 +288,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       panel_done = nullptr;
     }
   }
-  if (la.s2) {
-    // nothing may remain on the look-ahead stream past this point; make that explicit
+  // nothing may remain on the side streams past this point
+  for (hipStream_t side : {la.s2, la.s3}) {
+    if (!side) continue;
     hipEvent_t joined;
     if ((rc = la.event(&joined)) != LP_OK) return rc;
-    LP_HIP_TRY(hipEventRecord(joined, la.s2));
+    LP_HIP_TRY(hipEventRecord(joined, side));
     LP_HIP_TRY(hipStreamWaitEvent(s, joined, 0));
   }
   return LP_OK;
@@ -283,7 +315,7 @@ int factor_entry(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, in
     out->gemm_bytes = prof.gemm_bytes;
     out->panel_ms = Prof::total(prof.panel);
     out->panel_launches = (int)prof.panel.size();
-    out->swap_ms = Prof::total(prof.swap);
+    out->swap_ms = Prof::total(prof.swap) + Prof::total(prof.swapl);
     out->swap_bytes = prof.swap_bytes;
     out->trsm_ms = Prof::total(prof.trsm);
     out->trsm_flops = prof.trsm_flops;

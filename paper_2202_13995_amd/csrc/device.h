@@ -85,28 +85,30 @@ struct Mfma16<float> {
 // Cross-workgroup pivot-candidate slots (double-buffered by barrier parity):
 // per workgroup a key, a row index and the candidate row, plus the diagonal row
 // and its NaN flag.
+// Exchange records of one column parity: G candidate records, then the
+// diagonal record.  A record is kRecWords 64-bit words; word w < 2 * kLeafMax
+// holds 32 bits of the row (a double takes two words, low half first, a float
+// one), word 2 * kLeafMax the row index (candidate) or the NaN flag (diagonal).
+// Every word carries the writer's column tag in its upper 32 bits, so a reader
+// validates each word on its own: no word needs to be acknowledged before the
+// column's key is published.  Tags are unique within one factorization (the
+// records are zeroed when it starts).
+constexpr int kRecWords = 2 * kLeafMax + 2;
+
 struct LeafLayout {
-  size_t key_off, idx_off, rows_off, diag_off, flag_off, buf_bytes;
+  size_t rec_off, drec_off, buf_bytes;
 };
 
-template <typename T>
 __host__ __device__ inline LeafLayout leaf_layout(int G) {
   LeafLayout L;
-  size_t off = 0;
-  L.key_off = off;
-  off += sizeof(double) * (size_t)G;
-  L.idx_off = off;
-  off += sizeof(int) * (size_t)G;
-  off = (off + 15) & ~(size_t)15;
-  L.rows_off = off;
-  off += sizeof(T) * (size_t)G * kLeafMax;
-  L.diag_off = off;
-  off += sizeof(T) * kLeafMax;
-  L.flag_off = off;
-  off += 16;
-  off = (off + 255) & ~(size_t)255;
-  L.buf_bytes = off;
+  L.rec_off = 0;
+  L.drec_off = sizeof(unsigned long long) * kRecWords * (size_t)G;
+  L.buf_bytes = (L.drec_off + sizeof(unsigned long long) * kRecWords + 255) & ~(size_t)255;
   return L;
+}
+
+__device__ __forceinline__ unsigned long long tagged(unsigned tag, unsigned payload) {
+  return ((unsigned long long)tag << 32) | payload;
 }
 
 }  // namespace lp

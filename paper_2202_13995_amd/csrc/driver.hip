@@ -185,6 +185,8 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   if (n == 0) return LP_OK;
   if ((rc = launch_zero_words(work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
   if ((rc = launch_zero_words(work + L.keys0, panel_keys_bytes() / 4, s)) != LP_OK) return rc;
+  if ((rc = launch_zero_words(work + L.slots, leaf_slots_bytes(n, kLeafMax) / 4, s)) != LP_OK)
+    return rc;
   Factor<T> f{n, A, lda, ipiv, info, work + L.slots, (unsigned*)(work + L.barriers),
               (int)L.n_barriers, 0, work + L.staging, {work + L.keys0, work + L.keys1}, s};
   void* linv_trail = work + L.linv_trail;
@@ -428,6 +430,8 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
   if ((rc = launch_zero_words((char*)work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
   char* wk = (char*)work;
   if ((rc = launch_zero_words(wk + L.keys0, panel_keys_bytes() / 4, s)) != LP_OK) return rc;
+  if ((rc = launch_zero_words(wk + L.slots, leaf_slots_bytes(m, kLeafMax) / 4, s)) != LP_OK)
+    return rc;
   if (prec == LP_FP64) {
     Factor<double> f{m, (double*)A, lda, ipiv, info, wk + L.slots,
                      (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.staging,

@@ -65,8 +65,8 @@ int launch_convert(int to_f32, int rows, int cols, const void* src, long long ld
 size_t leaf_slots_bytes(int m, int w) {
   (void)m;
   (void)w;
-  // G <= 1024 workgroups, double-sized entries (covers float too)
-  return 2 * leaf_layout<double>(1024).buf_bytes;
+  // G <= 1024 workgroups, two column parities
+  return 2 * leaf_layout(1024).buf_bytes;
 }
 
 // ------------------------------------------------------- row interchanges

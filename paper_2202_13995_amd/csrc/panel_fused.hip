@@ -77,7 +77,6 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   __shared__ T drw[2][kLW];      // the diagonal row, by column parity
   __shared__ T prow[kLW];
   __shared__ T drow[kLW];
-  __shared__ int s_p;
   __shared__ int s_flag;
   __shared__ int s_piv[kLW];
   __shared__ int pl_nxt[kLW];
@@ -89,8 +88,10 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   __shared__ unsigned long long red_enc[4];
   __shared__ int red_g[4];
   __shared__ int s_timeout;
+  __shared__ int s_pw;
+  __shared__ int s_dflag;
 
-  const LeafLayout lay = leaf_layout<T>(G);
+  const LeafLayout lay = leaf_layout(G);
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -212,24 +213,32 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           drv = drw[par];
           urow = (p == dg) ? drv : wrow[par][wbest];
         } else {
-          // publish the row data, then the key: a non-zero key means "my slot
-          // for this column is complete"
+          // publish the candidate row and index (and, from the owner, the
+          // diagonal row and its NaN flag) as tagged words, then the key; a
+          // non-zero key says this workgroup reached the column, the tags say
+          // which words have landed
           char* sb = slots + (size_t)par * lay.buf_bytes;
-          int* sidx = reinterpret_cast<int*>(sb + lay.idx_off);
-          T* srows = reinterpret_cast<T*>(sb + lay.rows_off);
-          T* sdiag = reinterpret_cast<T*>(sb + lay.diag_off);
-          int* sflag = reinterpret_cast<int*>(sb + lay.flag_off);
+          unsigned long long* recs = reinterpret_cast<unsigned long long*>(sb + lay.rec_off);
+          unsigned long long* drec = reinterpret_cast<unsigned long long*>(sb + lay.drec_off);
           unsigned long long* ckeys = keys + (size_t)(dg - c0) * kMaxG;
-          if (tid == 0) xstore(&sidx[g], bi);
-          if (tid < wb && bi != INT_MAX) xstore(&srows[(size_t)g * kLeafMax + tid], wrow[par][wbest][tid]);
+          constexpr int kWPV = (int)(sizeof(T) / 4);  // 32-bit words per value
+          constexpr int kIdxW = 2 * kLeafMax;         // index / flag word
+          const int nw = kWPV * wb;
+          const unsigned tag = (unsigned)(dg + 1);
+          unsigned long long* myrec = recs + (size_t)g * kRecWords;
+          if (tid < nw && bi != INT_MAX)
+            xstore(&myrec[tid],
+                   tagged(tag, reinterpret_cast<const unsigned*>(wrow[par][wbest])[tid]));
+          if (tid == kIdxW) xstore(&myrec[kIdxW], tagged(tag, (unsigned)bi));
           if (own_diag) {
-            if (tid < wb) xstore(&sdiag[tid], drw[par][tid]);
-            if (tid == 64) {
+            if (tid >= 128 && tid < 128 + nw)
+              xstore(&drec[tid - 128],
+                     tagged(tag, reinterpret_cast<const unsigned*>(drw[par])[tid - 128]));
+            if (tid == 128 + kIdxW) {
               const T dv = drw[par][jj];
-              xstore(sflag, (dv != dv) ? 1 : 0);
+              xstore(&drec[kIdxW], tagged(tag, (dv != dv) ? 1u : 0u));
             }
           }
-          wg_sync();
           if (tid == 0) {
             unsigned long long ek = 1ull;  // no candidate
             if (bi != INT_MAX)
@@ -277,17 +286,44 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
               kv = red_enc[t];
               kg = red_g[t];
             }
-          // one round trip: winner's row and index, diagonal row, NaN flag
-          if (tid < wb) {
-            prow[tid] = xload(&srows[(size_t)kg * kLeafMax + tid]);
-            drow[tid] = xload(&sdiag[tid]);
+          // the winner's row and index, the diagonal row and its flag: read
+          // until every word carries this column's tag
+          {
+            const unsigned long long* wrec = recs + (size_t)kg * kRecWords;
+            unsigned* pbuf = reinterpret_cast<unsigned*>(prow);
+            unsigned* dbuf = reinterpret_cast<unsigned*>(drow);
+            const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+            for (;;) {
+              int bad = 0;
+              if (tid < nw) {
+                const unsigned long long w = xload(&wrec[tid]);
+                bad = (unsigned)(w >> 32) != tag;
+                pbuf[tid] = (unsigned)w;
+              } else if (tid == kIdxW) {
+                const unsigned long long w = xload(&wrec[kIdxW]);
+                bad = (unsigned)(w >> 32) != tag;
+                s_pw = (int)(unsigned)w;
+              } else if (tid >= 128 && tid < 128 + nw) {
+                const unsigned long long w = xload(&drec[tid - 128]);
+                bad = (unsigned)(w >> 32) != tag;
+                dbuf[tid - 128] = (unsigned)w;
+              } else if (tid == 128 + kIdxW) {
+                const unsigned long long w = xload(&drec[kIdxW]);
+                bad = (unsigned)(w >> 32) != tag;
+                s_dflag = (int)(unsigned)w;
+              }
+              if (!__syncthreads_or(bad)) break;
+              if (tid == 0 && __builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks)
+                s_timeout = 1;
+              __syncthreads();
+              if (s_timeout) {
+                if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
+                return false;
+              }
+              __builtin_amdgcn_s_sleep(1);
+            }
           }
-          if (tid == 64) {
-            const int pw = xload(&sidx[kg]);
-            s_p = xload(sflag) ? dg : pw;
-          }
-          __syncthreads();
-          p = s_p;
+          p = s_dflag ? dg : s_pw;
           drv = drow;
           urow = (p == dg) ? drv : prow;
         }
@@ -321,7 +357,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             for (int c = jj + 1; c < kLW; ++c) x[q][c] -= l * urow[c];
           }
         }
-        if (G > 1) __syncthreads();  // prow/drow/s_p are reused by the next column
+        if (G > 1) __syncthreads();  // prow/drow/s_pw/s_dflag are reused by the next column
       }
       return true;
     };

@@ -1,0 +1,154 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration bench.py
+times (look-ahead on, device-generated inputs from the same seed).
+
+The oracle cannot factor n = 32768 or 65536 in seconds, so these tests check
+what it can compute one by one and what holds at any size:
+  * sampled entries of P A = L U: rows of L and columns of U are copied back and
+    each sampled (P A)_ij is compared with sum_k l_ik u_kj on the host, within
+    gamma_n * sum_k |l_ik| |u_kj| (the componentwise backward-error bound of
+    Gaussian elimination);
+  * |l_ij| <= 1 on the sampled rows (partial pivoting) and ipiv[k] in [k, n);
+  * the first panel's pivots against the oracle's unblocked elimination of the
+    same n x nb panel (bit-exact pivot decisions);
+  * sampled rows of r = b - A x recomputed by the oracle from host-generated rows
+    of A, consistent with the device residual check, which must pass (s < 16).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2202_13995_amd as lp
+    return lp
+
+
+def sample_indices(n, nb, rng, k):
+    base = {0, 1, nb - 1, nb, nb + 1, n // 2, n - 2, n - 1}
+    extra = set(rng.integers(0, n, 4 * k).tolist())
+    return np.array(sorted(base | set(list(extra)[: max(0, k - len(base))])), dtype=np.int64)
+
+
+def check_factors(lp, F, ipiv, n, nb, seed, shift=0.0):
+    """Sampled P A = L U, |L| <= 1 and pivot validity on a device factorization F."""
+    import torch
+    rng = np.random.default_rng(seed)
+    piv = ipiv.cpu().numpy()[:n].astype(np.int64)
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    I = sample_indices(n, nb, rng, 16)
+    J = sample_indices(n, nb, rng, 16)
+    rows = F.index_select(0, torch.from_numpy(I).to(F.device)).cpu().numpy()       # |I| x n
+    cols = F.index_select(1, torch.from_numpy(J).to(F.device)).cpu().numpy()       # n x |J|
+    perm = oracle.perm_from_ipiv(piv, n)
+    a_rows = inputs.matrix_rows(seed, n, perm[I], shift=shift)                     # (P A)[I, :]
+    k = np.arange(n)
+    for t, i in enumerate(I):
+        l = rows[t].copy()
+        l[i] = 1.0
+        l[i + 1:] = 0.0
+        assert np.all(np.abs(l[:i]) <= 1.0), i
+        for s, j in enumerate(J):
+            u = np.where(k <= j, cols[:, s], 0.0)
+            terms = l * u
+            lu_ij = np.sum(terms)
+            bound = 4 * n * EPS * np.sum(np.abs(terms)) + 1e-300
+            assert abs(a_rows[t, j] - lu_ij) <= bound, (i, j, a_rows[t, j], lu_ij, bound)
+
+
+def check_residual(lp, X, out, n, seed, shift=0.0, nsample=64):
+    """Device residual passes; host rows of b - A x agree with its norms."""
+    s, rnorm, anorm, xnorm, bnorm = out[0]
+    assert s < 16.0, out
+    rng = np.random.default_rng(seed + 1)
+    I = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, nsample)]))
+    a_rows = inputs.matrix_rows(seed, n, I, shift=shift)
+    b_all = inputs.rhs(seed, n, 1)
+    x = X.cpu().numpy().reshape(n, 1)
+    r, absdot = oracle.row_residuals(a_rows, x, b_all[I])
+    # each sampled row's residual is within the device's max-norm
+    assert np.max(np.abs(r)) <= rnorm * (1 + 1e-12) + 4 * n * EPS * np.max(absdot)
+    # the device norms agree with the host data they summarize
+    assert np.max(np.sum(np.abs(a_rows), axis=1)) <= anorm * (1 + 1e-12)
+    assert xnorm == pytest.approx(float(np.max(np.abs(x))), rel=0, abs=0)
+    assert bnorm == pytest.approx(float(np.max(np.abs(b_all))), rel=0, abs=0)
+    # and the host-side scaled residual of the sampled rows passes on its own
+    s_host = np.max(np.abs(r)) / (EPS * (anorm * xnorm + bnorm) * n)
+    assert s_host < 16.0
+
+
+def run_fp64(lp, n, nb, seed):
+    import torch
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    inputs.fill_matrix_(A, seed)
+    B = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+    inputs.fill_rhs_(B, seed)
+    A0 = A.clone()
+    X = B.clone()
+    ipiv, info = lp.lu_factor(A, nb, "fp64", lookahead=True)
+    lp.lu_solve(A, ipiv, info, X)
+    out = lp.residual_check(A0, X, B).cpu().numpy()
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    return A, A0, ipiv, X, out
+
+
+def test_fp64_n32768_nb256(lp):
+    import torch
+    n, nb, seed = 32768, 256, 2202
+    F, A0, ipiv, X, out = run_fp64(lp, n, nb, seed)
+    del A0
+    check_factors(lp, F, ipiv, n, nb, seed)
+    check_residual(lp, X, out, n, seed)
+    # the first panel's pivots: the oracle's unblocked elimination of the same
+    # n x nb column panel
+    idx = (np.arange(n, dtype=np.uint64)[:, None] * np.uint64(n)
+           + np.arange(nb, dtype=np.uint64)[None, :])
+    panel = inputs.uniform(seed, inputs.STREAM_A, idx)
+    _, piv_o, info_o = oracle.getrf(panel)
+    assert info_o == 0
+    assert np.array_equal(ipiv.cpu().numpy()[:nb], piv_o[:nb])
+    del F
+    torch.cuda.empty_cache()
+
+
+def test_fp64_n65536_nb512(lp):
+    import torch
+    n, nb, seed = 65536, 512, 2202
+    F, A0, ipiv, X, out = run_fp64(lp, n, nb, seed)
+    del A0
+    check_factors(lp, F, ipiv, n, nb, seed)
+    check_residual(lp, X, out, n, seed)
+    del F
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("shift", [65536.0, 0.0])
+def test_mixed_bf16_n65536(lp, shift):
+    import torch
+    n, nb, seed = 65536, 512, 2202
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    inputs.fill_matrix_(A, seed, shift=shift)
+    B = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+    inputs.fill_rhs_(B, seed)
+    X, rep = lp.solve_ir(A, B, nb, "bf16")
+    r = rep.as_dict()
+    assert r["scaled_residual"] < 16 and r["converged"] == 1, r
+    if shift:
+        # diagonally dominant: refinement converges without the fallback
+        assert r["fell_back"] == 0 and r["iterations"] <= 6, r
+    else:
+        assert r["fell_back"] in (0, 1) and (r["fell_back"] == 0 or r["fallback_info"] == 0), r
+    out = lp.residual_check(A, X, B).cpu().numpy()
+    torch.cuda.synchronize()
+    assert out[0, 0] == pytest.approx(r["scaled_residual"], rel=1e-12)
+    check_residual(lp, X, out, n, seed, shift=shift)
+    del A
+    torch.cuda.empty_cache()

@@ -236,6 +236,10 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2202)
     ap.add_argument("--no-lookahead", action="store_true")
+    ap.add_argument("--panel-cus", type=int, default=0,
+                    help="compute units reserved for short panels (0 never, -1 automatic)")
+    ap.add_argument("--panel-rows", type=int, default=0,
+                    help="panels of at most this many rows use them (0 default)")
     ap.add_argument("--cpu-n", type=int, default=10240)
     ap.add_argument("--mixed-prec", default="bf16", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--mixed-n", type=int, default=0, help="default: --n")
@@ -298,7 +302,8 @@ def main() -> int:
     for w in range(W):
         scratch.copy_(A0)
         X = B0.clone()
-        lp.lu_factor(scratch, nb, "fp64", work=work, ipiv=ipiv, info=info, lookahead=look)
+        lp.lu_factor(scratch, nb, "fp64", work=work, ipiv=ipiv, info=info, lookahead=look,
+                     panel_cus=args.panel_cus, panel_rows=args.panel_rows)
         lp.lu_solve(scratch, ipiv, info, X)
         lp.residual_check(A0, X, B0)
         torch.cuda.synchronize()
@@ -314,7 +319,8 @@ def main() -> int:
     t0 = time.perf_counter()
     for i in range(K):
         _, _, prof = lp.lu_factor(As[i], nb, "fp64", work=work, ipiv=ipiv, info=infos[i],
-                                  lookahead=look, profile=True)
+                                  lookahead=look, profile=True, panel_cus=args.panel_cus,
+                                  panel_rows=args.panel_rows)
         lp.lu_solve(As[i], ipiv, infos[i], Xs[i])
         lp.residual_check(A0, Xs[i], B0, out=outs[i])
         profs.append(prof)
@@ -360,7 +366,8 @@ def main() -> int:
         "config": {"workload": f"FP64 blocked LU with partial pivoting + solve + residual "
                                f"check, n={n}, nb={nb}, nrhs={args.nrhs}, A and b "
                                f"uniform[-0.5,0.5) seed {args.seed}",
-                   "n": n, "nb": nb, "nrhs": args.nrhs, "lookahead": look},
+                   "n": n, "nb": nb, "nrhs": args.nrhs, "lookahead": look,
+                   "panel_cus": args.panel_cus, "panel_rows": args.panel_rows},
         "frac_fp64_peak": value / PEAK_FP64_TFLOPS,
         "scaled_residual_max": s_max,
         "residual_pass": bool(info_ok and s_max < 16.0),

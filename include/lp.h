@@ -95,8 +95,14 @@ int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t 
 
 /* Options and per-phase profile for lu_factor_ex. */
 typedef struct {
-  int lookahead; /* 1 (default): factor the next panel on a second stream while the
-                    rest of the inner-block update runs; 0: strictly in order */
+  int lookahead;  /* 1 (default): factor the next panel on a second stream while the
+                     rest of the inner-block update runs; 0: strictly in order */
+  int panel_cus;  /* compute units reserved for the panel once it is the longer
+                     chain (look-ahead only): 0 (default) never, -1 an eighth of
+                     a 256-CU device when n >= 8192, k > 0 k units (a multiple
+                     of 8; the CU mask interleaves over the XCDs) */
+  int panel_rows; /* panels of at most this many rows use the reserved units;
+                     0 (default): min(1024 * panel_cus, 3 n / 4) */
 } lp_factor_opts;
 
 typedef struct {

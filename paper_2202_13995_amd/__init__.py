@@ -46,7 +46,8 @@ class IRReport(ctypes.Structure):
 
 
 class FactorOpts(ctypes.Structure):
-    _fields_ = [("lookahead", ctypes.c_int)]
+    _fields_ = [("lookahead", ctypes.c_int), ("panel_cus", ctypes.c_int),
+                ("panel_rows", ctypes.c_int)]
 
 
 class FactorProfile(ctypes.Structure):
@@ -188,9 +189,12 @@ def workspace(n: int, nb: int, prec="fp64", device="cuda") -> torch.Tensor:
 
 
 def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
-              stream=None, lookahead: bool = True, profile: bool = False):
+              stream=None, lookahead: bool = True, profile: bool = False,
+              panel_cus: int = 0, panel_rows: int = 0):
     """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device, plus a
-    per-phase profile dict when profile=True (the call then synchronizes)."""
+    per-phase profile dict when profile=True (the call then synchronizes).
+    panel_cus / panel_rows: compute units reserved for short panels (see
+    lp_factor_opts in include/lp.h; 0 / 0: never)."""
     p = _prec(prec)
     lda = _mat(A, storage_dtype(p), "A")
     n = A.shape[0]
@@ -202,7 +206,7 @@ def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=
         ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
-    opts = FactorOpts(1 if lookahead else 0)
+    opts = FactorOpts(1 if lookahead else 0, panel_cus, panel_rows)
     prof = FactorProfile() if profile else None
     _check("lu_factor", _lib().lu_factor_ex(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
                                          info.data_ptr(), work.data_ptr(), work.numel(),

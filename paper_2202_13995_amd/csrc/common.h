@@ -72,11 +72,15 @@ size_t leaf_slots_bytes(int m, int w);
 size_t panel_staging_bytes(int W);
 // keys: this launch's zeroed key buffer; keys_next: the buffer of the next
 // panel launch on the same stream, which this launch zeroes.
+// max_wgs > 0: the launch runs on a stream restricted to that many compute
+// units, so it uses at most max_wgs workgroups (up to 1024 rows each) and
+// returns LP_ENOTSUP when the rows do not fit.
 size_t panel_keys_bytes();
+constexpr int kPanelRowsPerWg = 1024;
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s);
+                       void* keys_next, hipStream_t s, int max_wgs = 0);
 
 // Factorization / solve / residual (driver.hip, solve.hip), used by the IR driver.
 template <typename T>

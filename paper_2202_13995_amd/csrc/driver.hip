@@ -107,12 +107,12 @@ struct Factor {
   T* at(long long i, long long j) const { return A + i * lda + j; }
 
   // factor columns [j0, j0 + w) over rows [j0, m): one launch
-  int panel(int j0, int w) {
+  int panel(int j0, int w, int max_wgs = 0) {
     if (next_barrier >= n_barriers) return LP_ENOTSUP;
     const int idx = next_barrier++;
     unsigned* bar = barriers + idx;
     return launch_panel_fused<T>(m, j0, w, A, lda, ipiv, info, slots, bar, staging,
-                                 keys[idx & 1], keys[(idx + 1) & 1], s);
+                                 keys[idx & 1], keys[(idx + 1) & 1], s, max_wgs);
   }
 };
 
@@ -161,11 +161,14 @@ struct Prof {
 struct Lookahead {
   hipStream_t s2 = nullptr;  // the next panel
   hipStream_t s3 = nullptr;  // row exchanges left of the panel
+  // once panels are short: the panel on reserved compute units (sp), the rest
+  // of the step (sr) and the left exchanges (sr2) on the others
+  hipStream_t sp = nullptr, sr = nullptr, sr2 = nullptr;
   std::vector<hipEvent_t> ev;
   ~Lookahead() {
     for (auto e : ev) (void)hipEventDestroy(e);
-    if (s2) (void)hipStreamDestroy(s2);
-    if (s3) (void)hipStreamDestroy(s3);
+    for (hipStream_t x : {s2, s3, sp, sr, sr2})
+      if (x) (void)hipStreamDestroy(x);
   }
   int event(hipEvent_t* out) {
     hipEvent_t e;
@@ -176,9 +179,37 @@ struct Lookahead {
   }
 };
 
+// How one factorization schedules its work (lp_factor_opts).
+struct FactorCfg {
+  bool lookahead = true;
+  int panel_cus = 0;
+  int panel_rows = 0;
+};
+
+// Streams restricted by compute-unit masks: the first `reserve` mask bits for
+// the panel (the bits interleave over the XCDs, so every XCD gives
+// reserve / 8 units) and the other bits for the rest of the step.  On failure
+// the streams stay null and the factorization keeps the unmasked ones.
+bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
+  std::vector<uint32_t> mp((ncu + 31) / 32, 0u), mr((ncu + 31) / 32, 0u);
+  for (int b = 0; b < ncu; ++b) (b < reserve ? mp : mr)[b / 32] |= 1u << (b % 32);
+  const uint32_t words = (uint32_t)mp.size();
+  if (hipExtStreamCreateWithCUMask(&la.sp, words, mp.data()) == hipSuccess &&
+      hipExtStreamCreateWithCUMask(&la.sr, words, mr.data()) == hipSuccess &&
+      hipExtStreamCreateWithCUMask(&la.sr2, words, mr.data()) == hipSuccess)
+    return true;
+  (void)hipGetLastError();
+  for (hipStream_t* x : {&la.sp, &la.sr, &la.sr2})
+    if (*x) {
+      (void)hipStreamDestroy(*x);
+      *x = nullptr;
+    }
+  return false;
+}
+
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
-                char* work, hipStream_t s, bool lookahead, Prof& prof) {
+                char* work, hipStream_t s, const FactorCfg& cfg, Prof& prof) {
   const FactorLayout L = factor_layout(n, nb);
   int rc = launch_zero_words(info, 1, s);
   if (rc != LP_OK) return rc;
@@ -194,39 +225,58 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   void* plan_trail = plan_ring;  // the current step's plan
   const int npanels = (int)cdiv(n, nb);
   Lookahead la;
-  if (lookahead && npanels > 1) {
+  if (cfg.lookahead && npanels > 1) {
     LP_HIP_TRY(hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking));
     LP_HIP_TRY(hipStreamCreateWithFlags(&la.s3, hipStreamNonBlocking));
   }
-  // per ring slot: the left exchanges that read it (s3); the main stream waits
-  // for it before writing the slot again
+  // Optional reserved compute units for short panels.  While the trailing
+  // update is long it hides the panel; once the panels are short they are the
+  // longer chain, and on shared compute units their FP64 and LDS work queues
+  // behind the update's.  With panel_cus set, the panel then runs on its own
+  // units (at most one 1024-row workgroup each) and the update on the others.
+  // Off by default: measured on one MI355X at n = 32768 and 65536 the panel
+  // did not get faster on masked streams while the solve and exchanges on the
+  // complement slowed down.
+  const int ncu = num_cus();
+  int reserve = cfg.panel_cus < 0 ? (ncu == 256 && n >= 8192 ? 32 : 0) : cfg.panel_cus;
+  if (reserve < 8 || reserve % 8 != 0 || reserve >= ncu) reserve = 0;
+  const int cap_rows = reserve * kPanelRowsPerWg;
+  const int switch_rows =
+      std::min(cfg.panel_rows > 0 ? cfg.panel_rows : std::min(cap_rows, 3 * (n / 4)), cap_rows);
+  bool can_mask = la.s2 != nullptr && reserve > 0 && switch_rows > 0;
+  hipStream_t ms = s;      // the step's swaps, solve and update
+  hipStream_t ps = la.s2;  // the next panel
+  hipStream_t ls = la.s3;  // exchanges left of the panel
+  int pwgs = 0;            // workgroup cap of panel launches (0: whole chip)
+  // per ring slot: the left exchanges that read it; the main stream waits for
+  // it before writing the slot again
   hipEvent_t left_done[kPlanRing] = {nullptr, nullptr, nullptr, nullptr};
   const double es = sizeof(T);
 
-  // trailing steps of panel k on stream s over the column range [c0, c1) right of
-  // the panel (and, if left, the columns left of the panel for the exchanges)
+  // trailing steps of panel k on the main stream over the column range [c0, c1)
+  // right of the panel (and, if left, the columns left of the panel)
   auto trailing = [&](int j0, int w, int c0, int c1, bool left) -> int {
     const int j1 = j0 + w;
     int r;
-    if ((r = prof.begin(prof.swap, s)) != LP_OK) return r;
-    if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, s)) != LP_OK)
+    if ((r = prof.begin(prof.swap, ms)) != LP_OK) return r;
+    if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, ms)) != LP_OK)
       return r;
-    if ((r = prof.end(prof.swap, s)) != LP_OK) return r;
+    if ((r = prof.end(prof.swap, ms)) != LP_OK) return r;
     prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
     if (c1 <= c0) return LP_OK;
-    if ((r = prof.begin(prof.trsm, s)) != LP_OK) return r;
+    if ((r = prof.begin(prof.trsm, ms)) != LP_OK) return r;
     if ((r = launch_trsm_lower_unit<T>(w, c1 - c0, f.at(j0, j0), lda, f.at(j0, c0), lda,
-                                       linv_trail, s)) != LP_OK)
+                                       linv_trail, ms)) != LP_OK)
       return r;
-    if ((r = prof.end(prof.trsm, s)) != LP_OK) return r;
+    if ((r = prof.end(prof.trsm, ms)) != LP_OK) return r;
     prof.trsm_flops += 1.0 * w * w * (c1 - c0);
     const int M = n - j1, N = c1 - c0;
     if (M <= 0) return LP_OK;
-    if ((r = prof.begin(prof.gemm, s)) != LP_OK) return r;
+    if ((r = prof.begin(prof.gemm, ms)) != LP_OK) return r;
     if ((r = launch_gemm_update(prec, M, N, w, f.at(j1, j0), lda, f.at(j0, c0), lda,
-                                f.at(j1, c0), lda, s)) != LP_OK)
+                                f.at(j1, c0), lda, ms)) != LP_OK)
       return r;
-    if ((r = prof.end(prof.gemm, s)) != LP_OK) return r;
+    if ((r = prof.end(prof.gemm, ms)) != LP_OK) return r;
     prof.gemm_flops += 2.0 * M * N * w;
     prof.gemm_bytes += es * (2.0 * M * N + (double)M * w + (double)w * N);
     return LP_OK;
@@ -241,57 +291,76 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     const int j0 = k * nb;
     const int w = std::min(nb, n - j0);
     const int j1 = j0 + w;
-    if (panel_done) LP_HIP_TRY(hipStreamWaitEvent(s, panel_done, 0));
+    const bool more = k + 1 < npanels;
+    const int w2 = more ? std::min(nb, n - j1) : 0;
+    if (can_mask && more && n - j1 <= switch_rows) {
+      // from this step on: everything after the work already queued, on the
+      // masked streams
+      can_mask = false;
+      if (make_masked_streams(la, ncu, reserve)) {
+        hipEvent_t e1, e2;
+        if ((rc = la.event(&e1)) != LP_OK) return rc;
+        LP_HIP_TRY(hipEventRecord(e1, ms));
+        LP_HIP_TRY(hipStreamWaitEvent(la.sr, e1, 0));
+        if ((rc = la.event(&e2)) != LP_OK) return rc;
+        LP_HIP_TRY(hipEventRecord(e2, ls));
+        LP_HIP_TRY(hipStreamWaitEvent(la.sr2, e2, 0));
+        ms = la.sr;
+        ps = la.sp;
+        ls = la.sr2;
+        pwgs = reserve;
+      }
+    }
+    if (panel_done) LP_HIP_TRY(hipStreamWaitEvent(ms, panel_done, 0));
     const int slot = k % kPlanRing;
     plan_trail = plan_ring + (size_t)slot * L.plan_bytes;
-    if (left_done[slot]) LP_HIP_TRY(hipStreamWaitEvent(s, left_done[slot], 0));
+    if (left_done[slot]) LP_HIP_TRY(hipStreamWaitEvent(ms, left_done[slot], 0));
     if (j0 > 0 || j1 < n) {
-      if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, s)) != LP_OK) return rc;
+      if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, ms)) != LP_OK) return rc;
     }
-    if (la.s3 && j0 > 0) {
+    if (ls && j0 > 0) {
       // the exchanges left of the panel: nothing reads those columns before the
       // final join, so they run behind the main stream
       hipEvent_t plan_ready;
       if ((rc = la.event(&plan_ready)) != LP_OK) return rc;
-      LP_HIP_TRY(hipEventRecord(plan_ready, s));
-      LP_HIP_TRY(hipStreamWaitEvent(la.s3, plan_ready, 0));
-      if ((rc = prof.begin(prof.swapl, la.s3)) != LP_OK) return rc;
-      if ((rc = launch_swap_apply<T>(A, lda, 0, j0, 0, 0, w, plan_trail, la.s3)) != LP_OK)
-        return rc;
-      if ((rc = prof.end(prof.swapl, la.s3)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(plan_ready, ms));
+      LP_HIP_TRY(hipStreamWaitEvent(ls, plan_ready, 0));
+      if ((rc = prof.begin(prof.swapl, ls)) != LP_OK) return rc;
+      if ((rc = launch_swap_apply<T>(A, lda, 0, j0, 0, 0, w, plan_trail, ls)) != LP_OK) return rc;
+      if ((rc = prof.end(prof.swapl, ls)) != LP_OK) return rc;
       prof.swap_bytes += 2.0 * es * 2.0 * w * j0;
       if ((rc = la.event(&left_done[slot])) != LP_OK) return rc;
-      LP_HIP_TRY(hipEventRecord(left_done[slot], la.s3));
+      LP_HIP_TRY(hipEventRecord(left_done[slot], ls));
     }
-    const bool more = k + 1 < npanels;
-    const int w2 = more ? std::min(nb, n - j1) : 0;
-    if (more && la.s2) {
+    if (more && ps) {
       // the next panel's columns first, then factor it beside the rest
       if ((rc = trailing(j0, w, j1, j1 + w2, false)) != LP_OK) return rc;
       hipEvent_t next_ready;
       if ((rc = la.event(&next_ready)) != LP_OK) return rc;
-      LP_HIP_TRY(hipEventRecord(next_ready, s));
-      LP_HIP_TRY(hipStreamWaitEvent(la.s2, next_ready, 0));
-      f.s = la.s2;
-      if ((rc = prof.begin(prof.panel, la.s2)) != LP_OK) return rc;
-      if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
-      if ((rc = prof.end(prof.panel, la.s2)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(next_ready, ms));
+      LP_HIP_TRY(hipStreamWaitEvent(ps, next_ready, 0));
+      f.s = ps;
+      if ((rc = prof.begin(prof.panel, ps)) != LP_OK) return rc;
+      if ((rc = f.panel(j1, w2, pwgs)) != LP_OK) return rc;
+      if ((rc = prof.end(prof.panel, ps)) != LP_OK) return rc;
       f.s = s;
       if ((rc = la.event(&panel_done)) != LP_OK) return rc;
-      LP_HIP_TRY(hipEventRecord(panel_done, la.s2));
-      if ((rc = trailing(j0, w, j1 + w2, n, la.s3 == nullptr)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(panel_done, ps));
+      if ((rc = trailing(j0, w, j1 + w2, n, ls == nullptr)) != LP_OK) return rc;
     } else {
-      if ((rc = trailing(j0, w, j1, n, la.s3 == nullptr)) != LP_OK) return rc;
+      if ((rc = trailing(j0, w, j1, n, ls == nullptr)) != LP_OK) return rc;
       if (more) {
-        if ((rc = prof.begin(prof.panel, s)) != LP_OK) return rc;
+        f.s = ms;
+        if ((rc = prof.begin(prof.panel, ms)) != LP_OK) return rc;
         if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
-        if ((rc = prof.end(prof.panel, s)) != LP_OK) return rc;
+        if ((rc = prof.end(prof.panel, ms)) != LP_OK) return rc;
+        f.s = s;
       }
       panel_done = nullptr;
     }
   }
-  // nothing may remain on the side streams past this point
-  for (hipStream_t side : {la.s2, la.s3}) {
+  // nothing may remain on the other streams past this point
+  for (hipStream_t side : {la.s2, la.s3, la.sp, la.sr, la.sr2}) {
     if (!side) continue;
     hipEvent_t joined;
     if ((rc = la.event(&joined)) != LP_OK) return rc;
@@ -303,10 +372,10 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
 
 template <typename T>
 int factor_entry(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
-                 char* work, hipStream_t s, bool lookahead, lp_factor_profile* out) {
+                 char* work, hipStream_t s, const FactorCfg& cfg, lp_factor_profile* out) {
   Prof prof;
   prof.on = out != nullptr;
-  int rc = factor_impl<T>(n, nb, prec, A, lda, ipiv, info, work, s, lookahead, prof);
+  int rc = factor_impl<T>(n, nb, prec, A, lda, ipiv, info, work, s, cfg, prof);
   if (out != nullptr) {
     hipError_t e = hipStreamSynchronize(s);
     if (rc == LP_OK && e != hipSuccess) rc = LP_EHIP_BASE - (int)e;
@@ -365,13 +434,17 @@ int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32
   if (info == nullptr) return -7;
   if (work == nullptr) return -8;
   if (work_bytes < lu_workspace_bytes(n, nb, prec)) return LP_ENOSPC;
-  const bool lookahead = opts == nullptr || opts->lookahead != 0;
+  FactorCfg cfg;
+  if (opts != nullptr) {
+    cfg.lookahead = opts->lookahead != 0;
+    cfg.panel_cus = opts->panel_cus;
+    cfg.panel_rows = opts->panel_rows;
+  }
   hipStream_t s = (hipStream_t)stream;
   if (prec == LP_FP64)
-    return factor_entry<double>(n, nb, prec, (double*)A, lda, ipiv, info, (char*)work, s,
-                                lookahead, prof);
-  return factor_entry<float>(n, nb, prec, (float*)A, lda, ipiv, info, (char*)work, s, lookahead,
-                             prof);
+    return factor_entry<double>(n, nb, prec, (double*)A, lda, ipiv, info, (char*)work, s, cfg,
+                                prof);
+  return factor_entry<float>(n, nb, prec, (float*)A, lda, ipiv, info, (char*)work, s, cfg, prof);
 }
 
 int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info, void* work,

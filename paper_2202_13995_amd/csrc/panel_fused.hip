@@ -39,7 +39,8 @@
 namespace lp {
 namespace {
 
-constexpr int kLW = 32;          // leaf width
+constexpr int kLW = 32;          // the widest leaf (leaf width LW is 16 or 32)
+constexpr int kChunk = 256;      // rows per thread-sweep (one per thread); RPT chunks per workgroup
 constexpr int kMaxEnt = 2 * kLW;  // gather entries of one leaf's exchanges
 constexpr int kMaxG = 256;        // workgroups per panel launch
 constexpr int kKeySlots = 1024 * kMaxG;  // one key per (column, workgroup)
@@ -61,7 +62,7 @@ __device__ __forceinline__ void wg_sync() {
   __syncthreads();
 }
 
-template <typename T, int RPT>
+template <typename T, int RPT, int LW>
 __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     int m, int c0, int W, T* __restrict__ A, long long lda, int32_t* __restrict__ ipiv,
     int32_t* __restrict__ info, int R, int G, char* __restrict__ slots,
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   typedef Mfma16<T> MF;
   typedef typename MF::acc acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);  // [kLW][R] column-major
+  T* stage = reinterpret_cast<T*>(smem_raw);  // [LW][kChunk] column-major, one row chunk
+  __shared__ T lblk[kLW * (kLW + 1)];         // the leaf's own rows (diagonal block), row-major
   __shared__ double red_key[2][4];
   __shared__ int red_idx[2][4];
   __shared__ T wrow[2][4][kLW];  // each wave's candidate row, by column parity
@@ -101,11 +103,15 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   unsigned nbar = 0;
   // the first zero pivot so far (read once; only this launch writes it meanwhile)
   int info_val = (g == 0 && tid == 0) ? *info : 0;
-  // the next panel launch on this stream has at most W columns and G workgroups
-  if (G > 1) {
-    for (int e = g * blockDim.x + tid; e < W * G; e += G * blockDim.x)
-      xstore(&keys_next[(size_t)(e / G) * kMaxG + (e % G)], 0ull);
+  // the next panel launch has at most W columns; it may have more workgroups
+  // than this one, so every key slot of those columns is cleared
+  if (G > 1) {  // a single-workgroup launch is followed by single-workgroup launches
+    for (int e = g * blockDim.x + tid; e < W * kMaxG; e += G * blockDim.x)
+      xstore(&keys_next[e], 0ull);
   }
+  // the panel is the critical path while the trailing update runs beside it
+  // on the same compute units: its waves issue first
+  __builtin_amdgcn_s_setprio(3);
   if (tid == 0) s_timeout = 0;
 
   // every workgroup executes the same sequence of these
@@ -119,29 +125,32 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     return ok;
   };
 
-  const int nleaf = (W + kLW - 1) / kLW;
+  const int nleaf = (W + LW - 1) / LW;
   for (int b = 0; b < nleaf; ++b) {
-    const int cb = c0 + b * kLW;
-    const int wb = min(kLW, c0 + W - cb);
+    const int cb = c0 + b * LW;
+    const int wb = min(LW, c0 + W - cb);
     const int right0 = cb + wb;
     const int nright = c0 + W - right0;
     const int rlo = max(cb - base, 0);
 
-    // (A) the leaf's rows >= cb: coalesced loads into LDS, then each thread
-    // takes its rows into registers
-    for (int e = rlo * wb + tid; e < nrows * wb; e += blockDim.x) {
-      const int r = e / wb;
-      const int c = e - r * wb;
-      tile[c * R + r] = xload(&A[(long long)(base + r) * lda + cb + c]);
-    }
-    __syncthreads();
-    T x[RPT][kLW];
+    // (A) the leaf's rows >= cb, in chunks of 256 rows: coalesced loads into
+    // LDS, then each thread takes its row of the chunk into registers
+    T x[RPT][LW];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + 256 * q;
+      const int r0 = kChunk * q;
+      const int lo = max(rlo, r0), hi = min(nrows, r0 + kChunk);
+      for (int e = (lo - r0) * wb + tid; e < (hi - r0) * wb; e += blockDim.x) {
+        const int r = e / wb;
+        const int c = e - r * wb;
+        stage[c * kChunk + r] = xload(&A[(long long)(base + r0 + r) * lda + cb + c]);
+      }
+      __syncthreads();
+      const int r = r0 + tid;
       const bool act = r >= rlo && r < nrows;
 #pragma unroll
-      for (int c = 0; c < kLW; ++c) x[q][c] = (act && c < wb) ? tile[c * R + r] : T(0);
+      for (int c = 0; c < LW; ++c) x[q][c] = (act && c < wb) ? stage[c * kChunk + tid] : T(0);
+      __syncthreads();
     }
 
     // (B) the leaf's columns; the column index is a compile-time constant in
@@ -181,11 +190,11 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           const int gi = base + tid + 256 * q;
           if (bi != INT_MAX && gi == bi) {
 #pragma unroll
-            for (int c = 0; c < kLW; ++c) wrow[par][wave][c] = x[q][c];
+            for (int c = 0; c < LW; ++c) wrow[par][wave][c] = x[q][c];
           }
           if (gi == dg && tid + 256 * q < nrows) {
 #pragma unroll
-            for (int c = 0; c < kLW; ++c) drw[par][c] = x[q][c];
+            for (int c = 0; c < LW; ++c) drw[par][c] = x[q][c];
           }
         }
         if (lane == 0) {
@@ -344,41 +353,49 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           if (p != dg && r < nrows) {
             if (gi == p) {
 #pragma unroll
-              for (int c = 0; c < kLW; ++c) x[q][c] = drv[c];
+              for (int c = 0; c < LW; ++c) x[q][c] = drv[c];
             } else if (gi == dg) {
 #pragma unroll
-              for (int c = 0; c < kLW; ++c) x[q][c] = urow[c];
+              for (int c = 0; c < LW; ++c) x[q][c] = urow[c];
             }
           }
           if (piv != T(0) && r < nrows && gi > dg) {
             const T l = x[q][jj] / piv;
             x[q][jj] = l;
 #pragma unroll
-            for (int c = jj + 1; c < kLW; ++c) x[q][c] -= l * urow[c];
+            for (int c = jj + 1; c < LW; ++c) x[q][c] -= l * urow[c];
           }
         }
         if (G > 1) __syncthreads();  // prow/drow/s_pw/s_dflag are reused by the next column
       }
       return true;
     };
-    if (!static_for<0, kLW>(column)) return;
+    if (!static_for<0, LW>(column)) return;
 
-    // (C) the factored leaf to LDS (kept for the solve and the update), then
-    // coalesced stores to memory
+    // (C) the factored leaf back to memory in chunks of 256 rows (coalesced
+    // through LDS); the leaf's own rows also go to lblk for the solve in (E)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + 256 * q;
+      const int r0 = kChunk * q;
+      const int r = r0 + tid;
       if (r >= rlo && r < nrows) {
 #pragma unroll
-        for (int c = 0; c < kLW; ++c)
-          if (c < wb) tile[c * R + r] = x[q][c];
+        for (int c = 0; c < LW; ++c)
+          if (c < wb) stage[c * kChunk + tid] = x[q][c];
       }
-    }
-    __syncthreads();
-    for (int e = rlo * wb + tid; e < nrows * wb; e += blockDim.x) {
-      const int r = e / wb;
-      const int c = e - r * wb;
-      xstore(&A[(long long)(base + r) * lda + cb + c], tile[c * R + r]);
+      const int li = r - (cb - base);
+      if (li >= 0 && li < wb) {
+#pragma unroll
+        for (int c = 0; c < LW; ++c) lblk[li * (kLW + 1) + c] = x[q][c];
+      }
+      __syncthreads();
+      const int lo = max(rlo, r0), hi = min(nrows, r0 + kChunk);
+      for (int e = (lo - r0) * wb + tid; e < (hi - r0) * wb; e += blockDim.x) {
+        const int rr = e / wb;
+        const int c = e - rr * wb;
+        xstore(&A[(long long)(base + r0 + rr) * lda + cb + c], stage[c * kChunk + rr]);
+      }
+      __syncthreads();
     }
 
     // (D) the leaf's exchanges on the panel's other columns
@@ -419,23 +436,22 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     // (E) the leaf's rows right of the leaf: U = L_bb^-1 * A(leaf rows, right)
     if ((cb - c0) / R == g) {
       wg_sync();
-      const int lr = cb - base;
       for (int col = tid; col < nright; col += blockDim.x) {
-        T x[kLW];
+        T x[LW];
 #pragma unroll
-        for (int i = 0; i < kLW; ++i)
+        for (int i = 0; i < LW; ++i)
           x[i] = (i < wb) ? xload(&A[(long long)(cb + i) * lda + right0 + col]) : T(0);
 #pragma unroll
-        for (int i = 1; i < kLW; ++i) {
+        for (int i = 1; i < LW; ++i) {
           if (i < wb) {
             T acc = x[i];
 #pragma unroll
-            for (int k = 0; k < i; ++k) acc -= tile[k * R + lr + i] * x[k];
+            for (int k = 0; k < i; ++k) acc -= lblk[i * (kLW + 1) + k] * x[k];
             x[i] = acc;
           }
         }
 #pragma unroll
-        for (int i = 0; i < kLW; ++i)
+        for (int i = 0; i < LW; ++i)
           if (i < wb) xstore(&A[(long long)(cb + i) * lda + right0 + col], x[i]);
       }
     }
@@ -444,20 +460,28 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
       return;
     }
 
-    // (F) own rows below the leaf: A(r, right) -= L(r, leaf) * U(leaf, right)
+    // (F) own rows below the leaf: A(r, right) -= L(r, leaf) * U(leaf, right),
+    // one 256-row chunk at a time with the chunk's L values staged in LDS
     const int r_first = max(right0 - base, 0);
-    if (r_first < nrows) {
-      const int gq = lane >> 4;
-      const int l16 = lane & 15;
-      const int rb0 = r_first & ~15;
-      const int nrb = (nrows - rb0 + 15) >> 4;
-      const int ncb = (nright + 15) >> 4;
+    const int gq = lane >> 4;
+    const int l16 = lane & 15;
+    const int ncb = (nright + 15) >> 4;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r0 = kChunk * q;
+      const int lo = max(r_first, r0), hi = min(nrows, r0 + kChunk);
+      if (lo >= hi) continue;  // the same for the whole workgroup
+#pragma unroll
+      for (int c = 0; c < LW; ++c) stage[c * kChunk + tid] = x[q][c];
+      __syncthreads();
+      const int rb0 = (lo - r0) & ~15;  // chunk-relative
+      const int nrb = (hi - r0 - rb0 + 15) >> 4;
       for (int cbk = wave; cbk < ncb; cbk += 4) {
         const int col = right0 + 16 * cbk + l16;
         const bool colok = col < c0 + W;
-        T bfr[2][4];
+        T bfr[LW / 16][4];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
+        for (int s2 = 0; s2 < LW / 16; ++s2)
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int k = 16 * s2 + MF::kidx(gq, t);
@@ -467,39 +491,40 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           acc_t acc[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int rloc = rb0 + 16 * (rg + u);
+            const int rloc = r0 + rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = rloc + MF::drow(gq, v);
-              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
+              const bool ok = (rg + u < nrb) && row >= lo && row < hi && colok;
               acc[u][v] = ok ? -xload(&A[(long long)(base + row) * lda + col]) : T(0);
             }
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int row = rb0 + 16 * (rg + u) + l16;
-            const bool rowok = (rg + u < nrb) && row < nrows;
+            const int arow = rb0 + 16 * (rg + u) + l16;  // chunk-relative
+            const bool rowok = (rg + u < nrb) && arow < kChunk;
 #pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2)
+            for (int s2 = 0; s2 < LW / 16; ++s2)
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const int k = 16 * s2 + MF::kidx(gq, t);
-                const T a = (rowok && k < wb) ? tile[k * R + row] : T(0);
+                const T a = (rowok && k < wb) ? stage[k * kChunk + arow] : T(0);
                 acc[u] = MF::mma(a, bfr[s2][t], acc[u]);
               }
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int rloc = rb0 + 16 * (rg + u);
+            const int rloc = r0 + rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = rloc + MF::drow(gq, v);
-              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
+              const bool ok = (rg + u < nrb) && row >= lo && row < hi && colok;
               if (ok) xstore(&A[(long long)(base + row) * lda + col], -acc[u][v]);
             }
           }
         }
       }
+      __syncthreads();
     }
     wg_sync();
   }
@@ -513,45 +538,53 @@ size_t panel_keys_bytes() { return sizeof(unsigned long long) * (size_t)kKeySlot
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s) {
+                       void* keys_next, hipStream_t s, int max_wgs) {
   const int rows = m - c0;
   if (rows <= 0 || W <= 0) return LP_OK;
   if (W > rows) return LP_ENOTSUP;
   const int ncu = num_cus();
   int R, G;
-  constexpr int kRowsMax = (sizeof(T) == 8) ? 512 : 1024;  // 128 KB of LDS for the leaf
-  if (rows <= kRowsMax) {
-    R = (rows + 31) & ~31;
+  if (rows <= kPanelRowsPerWg) {
+    R = (rows + 31) & ~31;  // one workgroup: no cross-workgroup exchange
     G = 1;
+  } else if (max_wgs > 0) {
+    // a reserved set of compute units: as few workgroups as cover the rows
+    R = (int)cdiv(rows, max_wgs);
+    R = (R + 31) & ~31;
+    if (R < kChunk) R = kChunk;
+    if (R > kPanelRowsPerWg) return LP_ENOTSUP;
+    G = (int)cdiv(rows, R);
   } else {
+    // the whole chip: many small workgroups
     R = (int)cdiv(rows, std::min(ncu, 256));
     R = (R + 31) & ~31;
-    if (R < 256) R = 256;
+    if (R < kChunk) R = kChunk;
     G = (int)cdiv(rows, R);
   }
-  if (R > kRowsMax || G > ncu || G > kMaxG || W > 1024) return LP_ENOTSUP;
-  const size_t lds = sizeof(T) * (size_t)R * kLW;
-  if (R <= 256)
-    hipLaunchKernelGGL((panel_fused_kernel<T, 1>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
-                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
-                       (unsigned long long*)keys, (unsigned long long*)keys_next);
-  else if (R <= 512)
-    hipLaunchKernelGGL((panel_fused_kernel<T, 2>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
-                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
-                       (unsigned long long*)keys, (unsigned long long*)keys_next);
-  else if constexpr (sizeof(T) == 4)
-    hipLaunchKernelGGL((panel_fused_kernel<T, 4>), dim3(G), dim3(256), lds, s, m, c0, W, A, lda,
-                       ipiv, info, R, G, (char*)slots, barrier, (T*)staging,
-                       (unsigned long long*)keys, (unsigned long long*)keys_next);
+  if (R > kPanelRowsPerWg || G > ncu || G > kMaxG || W > 1024) return LP_ENOTSUP;
+  const size_t lds = sizeof(T) * (size_t)kChunk * kLW;
+  // 1024 binary64 rows per workgroup keep 16-wide leaves in registers
+#define LP_PANEL_LAUNCH(RPTV, LWV)                                                               \
+  hipLaunchKernelGGL((panel_fused_kernel<T, RPTV, LWV>), dim3(G), dim3(256), lds, s, m, c0, W, A, \
+                     lda,                                                                        \
+                     ipiv, info, R, G, (char*)slots, barrier, (T*)staging,                       \
+                     (unsigned long long*)keys, (unsigned long long*)keys_next)
+  if (R <= kChunk)
+    LP_PANEL_LAUNCH(1, 32);
+  else if (R <= 2 * kChunk)
+    LP_PANEL_LAUNCH(2, 32);
+  else if constexpr (sizeof(T) == 8)
+    LP_PANEL_LAUNCH(4, 16);
   else
-    return LP_ENOTSUP;
+    LP_PANEL_LAUNCH(4, 32);
+#undef LP_PANEL_LAUNCH
   LP_LAUNCH_CHECK();
   return LP_OK;
 }
 
 template int launch_panel_fused<double>(int, int, int, double*, long long, int32_t*, int32_t*,
-                                        void*, unsigned*, void*, void*, void*, hipStream_t);
+                                        void*, unsigned*, void*, void*, void*, hipStream_t, int);
 template int launch_panel_fused<float>(int, int, int, float*, long long, int32_t*, int32_t*,
-                                       void*, unsigned*, void*, void*, void*, hipStream_t);
+                                       void*, unsigned*, void*, void*, void*, hipStream_t, int);
 
 }  // namespace lp

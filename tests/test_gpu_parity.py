@@ -185,6 +185,26 @@ def test_lu_factor_solve_matches_oracle(lp, n, nb):
     assert np.all(res[:, 0] < 16)
 
 
+@pytest.mark.parametrize("n,nb", [(4096, 256), (9000, 128)])
+def test_reserved_panel_units_match_oracle(lp, n, nb):
+    """Every panel after the first on 32 reserved compute units (1024-row
+    workgroups with 16-wide leaves once a panel spans more than one), the rest
+    of each step on the other units."""
+    import torch
+    A = inputs.matrix(31 + n, n)
+    B = inputs.rhs(31 + n, n, 2)
+    tA, tB = cuda(A), cuda(B)
+    ipiv, info = lp.lu_factor(tA, nb, "fp64", panel_cus=32, panel_rows=n)
+    lp.lu_solve(tA, ipiv, info, tB)
+    lu_o, piv_o, info_o = oracle.getrf(A)
+    x_o = oracle.getrs(lu_o, piv_o, B)
+    assert int(host(info)[0]) == info_o == 0
+    assert np.array_equal(host(ipiv)[:n], piv_o)
+    x = host(tB)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    assert np.all(oracle.residual(A, x, B)[:, 0] < 16)
+
+
 def test_config1_parity(lp):
     """n = 1024, nb = 64, A and b uniform[-0.5, 0.5) from seed 2202."""
     import torch

@@ -148,7 +148,8 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, K, W, nrhs):
     }
 
 
-def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp):
+def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small_n_max=512,
+                  large_slots=8):
     """Open-loop Poisson stream of solves through the continuous-batching server.
 
     Sizes are log-uniform in [64, 4096], 1-8 right-hand sides, half binary64 and
@@ -175,8 +176,8 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp):
     def nb_for(n):
         return 64 if n <= 1024 else 128
 
-    with lp.Server(memory_bytes=int(mem_gib * 2**30), small_n_max=512, max_batch=256,
-                   batch_slots=4, large_slots=8) as sv:
+    with lp.Server(memory_bytes=int(mem_gib * 2**30), small_n_max=small_n_max, max_batch=256,
+                   batch_slots=4, large_slots=large_slots) as sv:
         # warm-up: one request of each route, untimed
         for (n, pr) in ((100, "fp64"), (100, lowp), (1500, "fp64"), (1500, lowp)):
             A = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -207,13 +208,23 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp):
                 time.sleep(1e-4)
         t_end = time.perf_counter() - t0
     lat = np.array([1e3 * (t_done[t] - t_arr[t][1]) for t in t_done])
+    classes = {}
+    for t in t_done:
+        i = t_arr[t][0]
+        n_i, pr_i = reqs[i][3], reqs[i][5]
+        key = ("batched" if res[t]["batched"] else "blocked") + "/" + pr_i + \
+              ("/n<1024" if n_i < 1024 else "/n>=1024")
+        classes.setdefault(key, []).append(1e3 * (t_done[t] - t_arr[t][1]))
+    by_class = {k: {"count": len(v), "p50_ms": float(np.percentile(v, 50)),
+                    "p99_ms": float(np.percentile(v, 99))} for k, v in sorted(classes.items())}
     total = sum(flops(q[3], q[4]) for q in reqs)
     span = t_end - float(arrivals[0])
     bad = [d for d in res.values() if d["status"] != 0 or not d["scaled_residual"] < 16.0]
     return {
         "workload": f"Poisson stream, {nreq} requests at {rate:g}/s offered, n log-uniform "
                     f"[64,4096], 1-8 rhs, half fp64 / half {lowp}+binary64 refinement, "
-                    f"A uniform[-0.5,0.5), n<=512 batched, pool {mem_gib:g} GiB",
+                    f"A uniform[-0.5,0.5), n<={small_n_max} batched, {large_slots} blocked-path "
+                    f"slots, pool {mem_gib:g} GiB",
         "requests": nreq, "offered_rate_per_s": rate,
         "achieved_rate_per_s": nreq / span,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -221,6 +232,7 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp):
         "aggregate_tflops": total / span / 1e12,
         "makespan_s": span,
         "batched_fraction": float(np.mean([d["batched"] for d in res.values()])),
+        "by_class": by_class,
         "fell_back": int(sum(d["fell_back"] for d in res.values())),
         "failed": len(bad),
     }
@@ -251,6 +263,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-gib", type=float, default=16.0)
     ap.add_argument("--serve-lowp", default="fp32", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--serve-small-n", type=int, default=512,
+                    help="requests up to this n run in the batched launch")
+    ap.add_argument("--serve-large-slots", type=int, default=8)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-mib", type=int, default=0,
@@ -395,7 +410,8 @@ def main() -> int:
         log(f"[bench] serving {args.serve_requests} requests at {args.serve_rate:g}/s ...")
         line["serving"] = bench_serving(lp, inputs, torch, dev, args.serve_requests,
                                         args.serve_rate, args.seed, args.serve_gib,
-                                        args.serve_lowp)
+                                        args.serve_lowp, args.serve_small_n,
+                                        args.serve_large_slots)
         log(f"[bench] serving done: p50 {line['serving']['p50_ms']:.2f} ms, "
             f"p99 {line['serving']['p99_ms']:.2f} ms")
     if calib is not None:

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -157,7 +158,89 @@ struct Prof {
   }
 };
 
-// RAII holder for the look-ahead stream and its events.
+// Look-ahead streams live for the process and are reused: destroying a stream
+// waits for its work, which would make every factorization synchronous for
+// the host.  A stream handed back may still hold work of the call that used it;
+// a later call appends behind it (a false dependency, never a wrong order).
+class StreamPool {
+ public:
+  hipError_t get(hipStream_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].dev == dev) {
+          *out = free_[i].s;
+          free_.erase(free_.begin() + (long)i);
+          return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+  }
+  void put(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back({dev, s});
+  }
+
+ private:
+  struct Entry {
+    int dev;
+    hipStream_t s;
+  };
+  std::mutex mu_;
+  std::vector<Entry> free_;
+};
+
+StreamPool& stream_pool() {
+  static StreamPool* pool = new StreamPool();  // never destroyed: streams outlive static teardown
+  return *pool;
+}
+
+// Ordering events are reused the same way; one is handed out again only once
+// it has completed, so no wait that names it can still be pending.
+class EventPool {
+ public:
+  hipError_t get(hipEvent_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].dev == dev && hipEventQuery(free_[i].e) == hipSuccess) {
+          *out = free_[i].e;
+          free_.erase(free_.begin() + (long)i);
+          return hipSuccess;
+        }
+    }
+    return hipEventCreateWithFlags(out, hipEventDisableTiming);
+  }
+  void put(hipEvent_t ev) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back({dev, ev});
+  }
+
+ private:
+  struct Entry {
+    int dev;
+    hipEvent_t e;
+  };
+  std::mutex mu_;
+  std::vector<Entry> free_;
+};
+
+EventPool& event_pool() {
+  static EventPool* pool = new EventPool();
+  return *pool;
+}
+
+// RAII holder for the look-ahead streams and their events.
 struct Lookahead {
   hipStream_t s2 = nullptr;  // the next panel
   hipStream_t s3 = nullptr;  // row exchanges left of the panel
@@ -166,13 +249,15 @@ struct Lookahead {
   hipStream_t sp = nullptr, sr = nullptr, sr2 = nullptr;
   std::vector<hipEvent_t> ev;
   ~Lookahead() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-    for (hipStream_t x : {s2, s3, sp, sr, sr2})
+    for (auto e : ev) event_pool().put(e);
+    for (hipStream_t x : {s2, s3})
+      if (x) stream_pool().put(x);
+    for (hipStream_t x : {sp, sr, sr2})  // masked streams (optional mode): not pooled
       if (x) (void)hipStreamDestroy(x);
   }
   int event(hipEvent_t* out) {
     hipEvent_t e;
-    LP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    LP_HIP_TRY(event_pool().get(&e));
     ev.push_back(e);
     *out = e;
     return LP_OK;
@@ -226,8 +311,8 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   const int npanels = (int)cdiv(n, nb);
   Lookahead la;
   if (cfg.lookahead && npanels > 1) {
-    LP_HIP_TRY(hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking));
-    LP_HIP_TRY(hipStreamCreateWithFlags(&la.s3, hipStreamNonBlocking));
+    LP_HIP_TRY(stream_pool().get(&la.s2));
+    LP_HIP_TRY(stream_pool().get(&la.s3));
   }
   // Optional reserved compute units for short panels.  While the trailing
   // update is long it hides the panel; once the panels are short they are the

@@ -16,11 +16,11 @@ each of its launches during the timed steps, its HBM traffic per launch from
 the committed rocprofv3 counter summary (null if the kernel source changed
 since), and the CPU oracle timed on a bounded sample on this host.
 
-Two more objects ride on the same line: `mixed_ir` (the same n solved through
-the low-precision factorization plus binary64 refinement, default bfloat16 on
-A + n I, with the binary64 path timed on that same system for the speedup)
-and `serving` (an open-loop Poisson stream through the continuous-batching
-server: p50/p99 latency and aggregate TFLOP/s).  One process, one GPU; prints
+Two more objects ride on the same line: `mixed_ir` (n = 65536 solved through
+the bfloat16 factorization plus binary64 refinement on A + n I, with the
+binary64 path timed on that same system for the speedup) and `serving` (an
+open-loop Poisson stream through the continuous-batching server: p50/p99
+latency overall and per request class, and aggregate TFLOP/s).  One process, one GPU; prints
 one JSON line on stdout, progress on stderr.
 """
 from __future__ import annotations
@@ -254,13 +254,15 @@ def main() -> int:
                     help="panels of at most this many rows use them (0 default)")
     ap.add_argument("--cpu-n", type=int, default=10240)
     ap.add_argument("--mixed-prec", default="bf16", choices=["bf16", "fp16", "fp32"])
-    ap.add_argument("--mixed-n", type=int, default=0, help="default: --n")
-    ap.add_argument("--mixed-nb", type=int, default=0, help="default: --nb")
+    ap.add_argument("--mixed-n", type=int, default=65536,
+                    help="order of the mixed-precision system (0: --n)")
+    ap.add_argument("--mixed-nb", type=int, default=512, help="0: --nb")
     ap.add_argument("--mixed-unshifted", action="store_true",
                     help="no n*I diagonal shift (refinement may fail and fall back)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-rate", type=float, default=400.0)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=100.0,
+                    help="offered requests per second (about 3/4 of the measured saturation)")
     ap.add_argument("--serve-gib", type=float, default=16.0)
     ap.add_argument("--serve-lowp", default="fp32", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--serve-small-n", type=int, default=512,

@@ -20,6 +20,8 @@
 // (w / 2, w % 2) as 4 x 4 fragments; K advances in slabs through two LDS
 // buffers (one barrier per slab); accumulators start at -C and the tile is
 // written back negated.  Tiles are numbered XCD-aware as in the FP64 kernel.
+#include <type_traits>
+
 #include "common.h"
 
 namespace lp {
@@ -73,21 +75,27 @@ __device__ __forceinline__ void tile_coords_lp(int tiles_m, int tiles_n, int& tm
 }
 
 template <Op OP>
-__global__ __launch_bounds__(256, 2) void sgemm_update_kernel(
-    int M, int N, int K, const float* __restrict__ A, long long lda, const float* __restrict__ B,
-    long long ldb, float* __restrict__ C, long long ldc, int tiles_m, int tiles_n) {
+struct LdsShape {
   typedef typename OpTraits<OP>::elem E;
+  static constexpr int BK = OpTraits<OP>::BK;
+  static constexpr int PAD = 16 / sizeof(E);  // 16-byte pad per row: conflict-free 16 B reads
+  static constexpr int LS = BK + PAD;         // LDS row stride (elements)
+  static constexpr int A_ELEMS = SBM * LS;    // one buffer of the A tile
+  static constexpr int B_ELEMS = SBN * LS;    // one buffer of the B tile, transposed [col][k]
+};
+
+// Any tile, any K: rolled slab loop with predicated loads, one slab of prefetch.
+template <Op OP>
+__device__ __forceinline__ void sgemm_update_body(
+    int M, int N, int K, const float* __restrict__ A, long long lda, const float* __restrict__ B,
+    long long ldb, float* __restrict__ C, long long ldc, int row0, int col0,
+    typename OpTraits<OP>::elem* As0, typename OpTraits<OP>::elem* Bs0) {
+  typedef typename OpTraits<OP>::elem E;
+  typedef LdsShape<OP> SH;
   constexpr int BK = OpTraits<OP>::BK;
   constexpr int KS = OpTraits<OP>::KSTEPS;
-  constexpr int PAD = 16 / sizeof(E);     // 16-byte pad per row: conflict-free 16 B reads
-  constexpr int LS = BK + PAD;            // LDS row stride (elements)
-  __shared__ __align__(16) E As[2][SBM * LS];
-  __shared__ __align__(16) E Bs[2][SBN * LS];  // transposed: [col][k]
+  constexpr int LS = SH::LS;
 
-  int tm, tn;
-  tile_coords_lp(tiles_m, tiles_n, tm, tn);
-  const int row0 = tm * SBM;
-  const int col0 = tn * SBN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -134,13 +142,13 @@ __global__ __launch_bounds__(256, 2) void sgemm_update_kernel(
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
       const int r = e / BK, k = e - r * BK;
-      As[buf][r * LS + k] = (E)ra[i];
+      As0[buf * SH::A_ELEMS + r * LS + k] = (E)ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int e = tid + 256 * i;
       const int k = e / SBN, c = e - k * SBN;
-      Bs[buf][c * LS + k] = (E)rb[i];
+      Bs0[buf * SH::B_ELEMS + c * LS + k] = (E)rb[i];
     }
   };
 
@@ -151,8 +159,8 @@ __global__ __launch_bounds__(256, 2) void sgemm_update_kernel(
   for (int s = 0; s < nk; ++s) {
     const int buf = s & 1;
     if (s + 1 < nk) gload((s + 1) * BK);
-    const E* as = As[buf];
-    const E* bs = Bs[buf];
+    const E* as = As0 + buf * SH::A_ELEMS;
+    const E* bs = Bs0 + buf * SH::B_ELEMS;
     if constexpr (OP == Op::F32) {
       // lane group g owns k = 4g .. 4g+3; step t uses k = 4g + t
       f4 a4[4], b4[4];
@@ -206,6 +214,184 @@ __global__ __launch_bounds__(256, 2) void sgemm_update_kernel(
     }
 }
 
+template <Op OP>
+__global__ __launch_bounds__(256, 2) void sgemm_update_kernel(
+    int M, int N, int K, const float* __restrict__ A, long long lda, const float* __restrict__ B,
+    long long ldb, float* __restrict__ C, long long ldc, int tiles_m, int tiles_n) {
+  typedef typename OpTraits<OP>::elem E;
+  __shared__ __align__(16) E As[2 * LdsShape<OP>::A_ELEMS];
+  __shared__ __align__(16) E Bs[2 * LdsShape<OP>::B_ELEMS];
+  int tm, tn;
+  tile_coords_lp(tiles_m, tiles_n, tm, tn);
+  sgemm_update_body<OP>(M, N, K, A, lda, B, ldb, C, ldc, tm * SBM, tn * SBN, As, Bs);
+}
+
+template <int I, int END>
+struct StaticForLp {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&& f) {
+    if constexpr (I < END) {
+      f(std::integral_constant<int, I>{});
+      StaticForLp<I + 1, END>::run(f);
+    }
+  }
+};
+
+constexpr unsigned kRsrcWord3Lp = 0x00020000u;  // raw buffer, 32-bit data format
+
+// Interior tiles of the bfloat16 / half update with K = 32 * NK.  The binary32
+// operand slabs are prefetched two slabs ahead through two register sets
+// (16-byte buffer loads with 32-bit offsets), narrowed as they are written to
+// LDS (A negated there), the accumulators start at C (read in the prologue
+// beside the first two slabs) and the slab sequence is unrolled, so each LDS
+// write waits only for its own slab.  A one-step bfloat16 MFMA slab is short,
+// so the two slabs in flight per workgroup are what keeps the loads streaming.
+// Edge tiles and other K take sgemm_update_body.  Both compute every element
+// as the same sequence of rounded steps.
+template <Op OP, int NK>
+__global__ __launch_bounds__(256, 2) void sgemm_update_fast(
+    int M, int N, int K, const float* __restrict__ A, long long lda, const float* __restrict__ B,
+    long long ldb, float* __restrict__ C, long long ldc, int tiles_m, int tiles_n) {
+  typedef typename OpTraits<OP>::elem E;
+  typedef LdsShape<OP> SH;
+  constexpr int LS = SH::LS;
+  typedef typename std::conditional<OP == Op::BF16, bf16x8, f16x8>::type v8;
+  typedef E e4 __attribute__((ext_vector_type(4)));
+  __shared__ __align__(16) E As[2 * SH::A_ELEMS];
+  __shared__ __align__(16) E Bs[2 * SH::B_ELEMS];
+  int tm, tn;
+  tile_coords_lp(tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * SBM, col0 = tn * SBN;
+  if (!(row0 + SBM <= M && col0 + SBN <= N && K == 32 * NK)) {
+    sgemm_update_body<OP>(M, N, K, A, lda, B, ldb, C, ldc, row0, col0, As, Bs);
+    return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int a_k = (tid & 7) * 4, a_r = tid >> 3;   // A: k quad, rows a_r + 32 p
+  const int b_c = (tid & 31) * 4, b_k = tid >> 5;  // B: column quad, k rows b_k + 8 p
+
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A + (long long)row0 * lda), (short)0, 0x7fffffff, kRsrcWord3Lp);
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(B + col0), (short)0, 0x7fffffff, kRsrcWord3Lp);
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(C + (long long)(row0 + wm) * ldc + col0 + wn), (short)0, 0x7fffffff, kRsrcWord3Lp);
+  const int a_vo = (int)(((long long)a_r * lda + a_k) * 4);
+  const int b_vo = (int)(((long long)b_k * ldb + b_c) * 4);
+  const int c_vo = (int)(((long long)(4 * g) * ldc + l16) * 4);
+  const int a_so = (int)(32 * lda * 4);
+  const int b_so = (int)(8 * ldb * 4);
+  const int b_slab = (int)(32 * ldb * 4);
+
+  f4 rA[2][4], rB[2][4];
+  auto load = [&](f4* xa, f4* xb, int s) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      xa[p] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(ra, a_vo + s * 128,
+                                                                            p * a_so, 0));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      xb[p] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rb, b_vo + s * b_slab,
+                                                                            p * b_so, 0));
+  };
+  auto store = [&](const f4* xa, const f4* xb, int buf) {
+    E* as = As + buf * SH::A_ELEMS;
+    E* bs = Bs + buf * SH::B_ELEMS;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      e4 v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = -(E)xa[p][i];
+      *reinterpret_cast<e4*>(as + (a_r + 32 * p) * LS + a_k) = v;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bs[(b_c + i) * LS + b_k + 8 * p] = (E)xb[p][i];
+  };
+  f4 acc[4][4];
+  auto mfma_rows = [&](int buf, int i0, int i1) {
+    const E* as = As + buf * SH::A_ELEMS;
+    const E* bs = Bs + buf * SH::B_ELEMS;
+    v8 b8[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b8[j] = *reinterpret_cast<const v8*>(bs + (wn + 16 * j + l16) * LS + 8 * g);
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      const v8 a8 = *reinterpret_cast<const v8*>(as + (wm + 16 * i + l16) * LS + 8 * g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (OP == Op::BF16)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8[j], acc[i][j], 0, 0, 0);
+        else
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a8, b8[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+
+  load(rA[0], rB[0], 0);
+  if constexpr (NK > 1) load(rA[1], rB[1], 1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j][v] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(
+                       rc, c_vo + j * 64, (int)((long long)(16 * i + v) * ldc * 4), 0));
+  store(rA[0], rB[0], 0);
+  __syncthreads();
+  StaticForLp<0, NK>::run([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    constexpr int cur = s & 1, nxt = cur ^ 1;
+    if constexpr (s + 2 < NK) load(rA[cur], rB[cur], s + 2);
+    mfma_rows(cur, 0, 2);
+    if constexpr (s + 1 < NK) store(rA[nxt], rB[nxt], nxt);
+    mfma_rows(cur, 2, 4);
+    __syncthreads();
+  });
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = col0 + wn + 16 * j + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + wm + 16 * i + 4 * g + v;
+        C[(long long)r * ldc + c] = acc[i][j][v];
+      }
+    }
+}
+
+template <Op OP>
+bool launch_fast(int M, int N, int K, const float* A, long long lda, const float* B,
+                 long long ldb, float* C, long long ldc, int tiles_m, int tiles_n, hipStream_t s) {
+  const bool ok = ((((uintptr_t)A | (uintptr_t)B) & 15) == 0) && ((lda | ldb) & 3) == 0 &&
+                  (long long)SBM * lda * 4 < 0x7fffffffLL &&
+                  (long long)K * ldb * 4 < 0x7fffffffLL &&
+                  (long long)64 * ldc * 4 < 0x7fffffffLL && K % 32 == 0;
+  if (!ok) return false;
+  const dim3 grid((unsigned)((long long)tiles_m * tiles_n));
+  switch (K / 32) {
+#define LP_FAST_CASE(NKV)                                                                        \
+  case NKV:                                                                                      \
+    hipLaunchKernelGGL((sgemm_update_fast<OP, NKV>), grid, dim3(256), 0, s, M, N, K, A, lda, B, \
+                       ldb, C, ldc, tiles_m, tiles_n);                                           \
+    return true;
+    LP_FAST_CASE(2)
+    LP_FAST_CASE(4)
+    LP_FAST_CASE(8)
+    LP_FAST_CASE(16)
+    LP_FAST_CASE(32)
+#undef LP_FAST_CASE
+    default:
+      return false;
+  }
+}
+
 }  // namespace
 
 int launch_gemm_update_lp(int prec, int M, int N, int K, const float* A, long long lda,
@@ -219,12 +405,15 @@ int launch_gemm_update_lp(int prec, int M, int N, int K, const float* A, long lo
   if (prec == LP_FP32)
     hipLaunchKernelGGL(sgemm_update_kernel<Op::F32>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
                        ldb, C, ldc, tiles_m, tiles_n);
-  else if (prec == LP_BF16)
-    hipLaunchKernelGGL(sgemm_update_kernel<Op::BF16>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
-                       ldb, C, ldc, tiles_m, tiles_n);
-  else if (prec == LP_FP16)
-    hipLaunchKernelGGL(sgemm_update_kernel<Op::F16>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
-                       ldb, C, ldc, tiles_m, tiles_n);
+  else if (prec == LP_BF16) {
+    if (!launch_fast<Op::BF16>(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, s))
+      hipLaunchKernelGGL(sgemm_update_kernel<Op::BF16>, grid, dim3(256), 0, s, M, N, K, A, lda,
+                         B, ldb, C, ldc, tiles_m, tiles_n);
+  } else if (prec == LP_FP16) {
+    if (!launch_fast<Op::F16>(M, N, K, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, s))
+      hipLaunchKernelGGL(sgemm_update_kernel<Op::F16>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
+                         ldb, C, ldc, tiles_m, tiles_n);
+  }
   else
     return LP_ENOTSUP;
   LP_LAUNCH_CHECK();

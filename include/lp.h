@@ -295,6 +295,18 @@ int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void 
 int lp_gemm_update(int prec, int M, int N, int K, const void *A, int lda, const void *B,
                    int ldb, void *C, int ldc, void *stream);
 
+/* The bfloat16 / half form of the update above (prec LP_BF16 or LP_FP16
+ * only; K <= 1024) through packed operands: -A and B^T are first written to
+ * work, rounded to the 16-bit format (nearest even), as rows of k-contiguous
+ * values padded with zeros to 256-row tiles and a power-of-two multiple of 64
+ * in k; then C := C - A B on 256 x 256 tiles with binary32 accumulation.  The
+ * factorization uses this form for large trailing updates.  work: device
+ * scratch of lp_gemm_packed_workspace_bytes(M, N, K) bytes, 16-byte aligned,
+ * overwritten; LP_ENOSPC if smaller. */
+size_t lp_gemm_packed_workspace_bytes(int M, int N, int K);
+int lp_gemm_update_packed(int prec, int M, int N, int K, const void *A, int lda, const void *B,
+                          int ldb, void *C, int ldc, void *work, size_t work_bytes, void *stream);
+
 /* Element-wise copies between binary64 and binary32 (row-major, rows x cols):
  * to_f32 != 0 converts src double -> dst float (round to nearest even),
  * else src float -> dst double. */

@@ -117,6 +117,8 @@ SIGNATURES = {
     "lp_trsm_workspace_bytes": (_SZ, [_I]),
     "lp_trsm_lower_unit": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
     "lp_gemm_update": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
+    "lp_gemm_packed_workspace_bytes": (_SZ, [_I, _I, _I]),
+    "lp_gemm_update_packed": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
     "lp_convert": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
 }
 
@@ -419,6 +421,28 @@ def gemm_update(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=None,
         raise ValueError("shape mismatch")
     _check("lp_gemm_update", _lib().lp_gemm_update(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
                                                 C.data_ptr(), ldc, _stream(stream)))
+
+
+def gemm_update_packed(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=BF16,
+                       work=None, stream=None) -> None:
+    """C := C - A B (binary32 storage) through packed bfloat16 / half operands."""
+    p = _prec(prec)
+    lda = _mat(A, torch.float32, "A")
+    ldb = _mat(B, torch.float32, "B")
+    ldc = _mat(C, torch.float32, "C")
+    M, K = A.shape
+    N = B.shape[1]
+    if B.shape[0] != K or C.shape != (M, N):
+        raise ValueError("shape mismatch")
+    nbytes = _lib().lp_gemm_packed_workspace_bytes(M, N, K)
+    if nbytes == 0:
+        raise ValueError("unsupported size")
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=C.device)
+    _check("lp_gemm_update_packed",
+           _lib().lp_gemm_update_packed(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                        C.data_ptr(), ldc, work.data_ptr(), work.numel(),
+                                        _stream(stream)))
 
 
 def convert(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -48,6 +48,15 @@ int launch_gemm_update(int prec, int M, int N, int K, const void* A, long long l
 // binary32 storage: C := C - A B with operands on FP32, BF16 or FP16 MFMA.
 int launch_gemm_update_lp(int prec, int M, int N, int K, const float* A, long long lda,
                           const float* B, long long ldb, float* C, long long ldc, hipStream_t s);
+// The same update for bfloat16 / half through operands packed into pa (-A,
+// gemm_lp_packed_bytes(M, K) bytes; written only when pack_a) and pb (B^T,
+// gemm_lp_packed_bytes(N, K) bytes), 16-byte aligned.  Pays off when
+// gemm_lp_packed_pays (enough 256 x 256 tiles to fill the device).
+size_t gemm_lp_packed_bytes(int rows, int K);
+bool gemm_lp_packed_pays(int prec, int M, int N, int K);
+int launch_gemm_update_lp_packed(int prec, int M, int N, int K, const float* A, long long lda,
+                                 const float* B, long long ldb, float* C, long long ldc,
+                                 void* pa, void* pb, bool pack_a, hipStream_t s);
 
 // B := L^-1 B, L unit lower m x m (m <= 512); work: trsm_workspace_bytes(m).
 size_t trsm_workspace_bytes(int m);

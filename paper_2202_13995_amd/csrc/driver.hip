@@ -61,11 +61,12 @@ constexpr int kPlanRing = 4;
 
 struct FactorLayout {
   size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, plan_bytes, linv_trail,
-      total;
+      pack_a, pack_b, total;
 };
 
-FactorLayout factor_layout(int n, int nb) {
-  (void)nb;
+bool packs_operands(int prec) { return prec == LP_BF16 || prec == LP_FP16; }
+
+FactorLayout factor_layout(int n, int nb, int prec) {
   FactorLayout L;
   size_t off = 0;
   L.barriers = off;
@@ -84,6 +85,15 @@ FactorLayout factor_layout(int n, int nb) {
   off += kPlanRing * L.plan_bytes;
   L.linv_trail = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
+  // bfloat16 / half: the packed operands of the trailing update (-L of the
+  // step; U^T of a column range, placed at a 256-row offset per range)
+  L.pack_a = L.pack_b = 0;
+  if (packs_operands(prec)) {
+    L.pack_a = off;
+    off = align_up(off + gemm_lp_packed_bytes(n, nb), 256);
+    L.pack_b = off;
+    off = align_up(off + gemm_lp_packed_bytes(n + 1024, nb), 256);
+  }
   L.total = off;
   return L;
 }
@@ -295,7 +305,7 @@ bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
                 char* work, hipStream_t s, const FactorCfg& cfg, Prof& prof) {
-  const FactorLayout L = factor_layout(n, nb);
+  const FactorLayout L = factor_layout(n, nb, prec);
   int rc = launch_zero_words(info, 1, s);
   if (rc != LP_OK) return rc;
   if (n == 0) return LP_OK;
@@ -337,6 +347,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   // it before writing the slot again
   hipEvent_t left_done[kPlanRing] = {nullptr, nullptr, nullptr, nullptr};
   const double es = sizeof(T);
+  int packed_step = -1;  // the step whose -L is in the packed buffer
 
   // trailing steps of panel k on the main stream over the column range [c0, c1)
   // right of the panel (and, if left, the columns left of the panel)
@@ -358,9 +369,20 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     const int M = n - j1, N = c1 - c0;
     if (M <= 0) return LP_OK;
     if ((r = prof.begin(prof.gemm, ms)) != LP_OK) return r;
-    if ((r = launch_gemm_update(prec, M, N, w, f.at(j1, j0), lda, f.at(j0, c0), lda,
-                                f.at(j1, c0), lda, ms)) != LP_OK)
+    if (L.pack_a != 0 && gemm_lp_packed_pays(prec, M, N, w)) {
+      // -L packed once per step (both column ranges of the step run on this
+      // stream, in order); U^T of this range at its own rows
+      const size_t brow = (size_t)(c0 - j1 + 255) / 256 * 256;
+      char* pb = work + L.pack_b + gemm_lp_packed_bytes((int)brow, w);
+      r = launch_gemm_update_lp_packed(prec, M, N, w, (const float*)f.at(j1, j0), lda,
+                                       (const float*)f.at(j0, c0), lda, (float*)f.at(j1, c0), lda,
+                                       work + L.pack_a, pb, packed_step != j0, ms);
+      if (r != LP_OK) return r;
+      packed_step = j0;
+    } else if ((r = launch_gemm_update(prec, M, N, w, f.at(j1, j0), lda, f.at(j0, c0), lda,
+                                       f.at(j1, c0), lda, ms)) != LP_OK) {
       return r;
+    }
     if ((r = prof.end(prof.gemm, ms)) != LP_OK) return r;
     prof.gemm_flops += 2.0 * M * N * w;
     prof.gemm_bytes += es * (2.0 * M * N + (double)M * w + (double)w * N);
@@ -503,7 +525,7 @@ const char* lp_strerror(int code) {
 
 size_t lu_workspace_bytes(int n, int nb, int prec) {
   if (n < 0 || n > kMaxN || nb < 1 || nb > kMaxNb || !valid_prec(prec)) return 0;
-  return factor_layout(n, nb).total;
+  return factor_layout(n, nb, prec).total;
 }
 
 int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
@@ -582,7 +604,7 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
   if (work == nullptr) return -8;
   if (work_bytes < lu_workspace_bytes(m, std::max(1, w), prec)) return LP_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
-  const FactorLayout L = factor_layout(m, std::max(1, w));
+  const FactorLayout L = factor_layout(m, std::max(1, w), prec);
   int rc = launch_zero_words(info, 1, s);
   if (rc != LP_OK || w == 0) return rc;
   if ((rc = launch_zero_words((char*)work + L.barriers, L.n_barriers, s)) != LP_OK) return rc;
@@ -664,6 +686,33 @@ int lp_gemm_update(int prec, int M, int N, int K, const void* A, int lda, const 
   if (C == nullptr && M > 0 && N > 0) return -9;
   if (ldc < std::max(1, N)) return -10;
   return launch_gemm_update(prec, M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+}
+
+size_t lp_gemm_packed_workspace_bytes(int M, int N, int K) {
+  if (M < 0 || N < 0 || K < 0 || K > 1024) return 0;
+  const size_t a = gemm_lp_packed_bytes(std::max(M, 1), std::max(K, 1));
+  return align_up(a, 256) + gemm_lp_packed_bytes(std::max(N, 1), std::max(K, 1));
+}
+
+int lp_gemm_update_packed(int prec, int M, int N, int K, const void* A, int lda, const void* B,
+                          int ldb, void* C, int ldc, void* work, size_t work_bytes, void* stream) {
+  if (!packs_operands(prec)) return -1;
+  if (M < 0) return -2;
+  if (N < 0) return -3;
+  if (K < 0 || K > 1024) return -4;
+  if (A == nullptr && M > 0 && K > 0) return -5;
+  if (lda < std::max(1, K)) return -6;
+  if (B == nullptr && K > 0 && N > 0) return -7;
+  if (ldb < std::max(1, N)) return -8;
+  if (C == nullptr && M > 0 && N > 0) return -9;
+  if (ldc < std::max(1, N)) return -10;
+  if (work == nullptr) return -11;
+  if (work_bytes < lp_gemm_packed_workspace_bytes(M, N, K)) return LP_ENOSPC;
+  if (M == 0 || N == 0 || K == 0) return LP_OK;
+  char* w = (char*)work;
+  return launch_gemm_update_lp_packed(
+      prec, M, N, K, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc, w,
+      w + align_up(gemm_lp_packed_bytes(M, K), 256), true, (hipStream_t)stream);
 }
 
 int lp_convert(int to_f32, int rows, int cols, const void* src, int lds, void* dst, int ldd,

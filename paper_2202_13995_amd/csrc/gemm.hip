@@ -88,7 +88,9 @@ struct Roles {
   int a_k, a_r;        // A staging: k pair a_k, rows a_r + 32 p
   int b_c, b_k;        // B staging: column pair b_c, k rows b_k + 4 p
   __device__ __forceinline__ Roles() {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index is uniform; saying so keeps buffer descriptors built from
+    // it in SGPRs (no per-lane descriptor loops)
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     wm = (wave >> 1) * 64;
     wn = (wave & 1) * 64;
     l16 = lane & 15;

@@ -65,7 +65,9 @@ IRLayout ir_layout(int n, int nb, int prec, int nrhs) {
   L.big = off;  // binary32 copy of A; reused for the binary64 copy of the fallback
   off = align_up(off + sizeof(double) * (size_t)n * n, 256);
   L.fwork = off;
-  off = align_up(off + lu_workspace_bytes(n, nb, prec), 256);
+  // the low-precision factorization and the binary64 fallback share it
+  off = align_up(off + std::max(lu_workspace_bytes(n, nb, prec), lu_workspace_bytes(n, nb, LP_FP64)),
+                 256);
   L.ipiv = off;
   off = align_up(off + sizeof(int32_t) * (size_t)std::max(n, 1), 256);
   L.info = off;

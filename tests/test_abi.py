@@ -57,3 +57,9 @@ def test_argument_checks_without_device():
     assert L.lu_solve(4, 5, None, 4, None, None, None, 1, 1, None, None) == -2
     assert L.residual_check(-1, None, 1, None, 1, None, 1, 1, None, None) == -1
     assert L.lp_gemm_update(0, -1, 1, 1, None, 1, None, 1, None, 1, None) == -2
+    # packed bfloat16 / half update: precision and size limits, workspace first
+    assert L.lp_gemm_update_packed(0, 1, 1, 1, None, 1, None, 1, None, 1, None, 0, None) == -1
+    assert L.lp_gemm_update_packed(2, 1, 1, 1025, None, 1025, None, 1, None, 1, None, 0, None) == -4
+    assert L.lp_gemm_packed_workspace_bytes(100, 100, 2000) == 0
+    # padded to 256-row tiles and a power-of-two multiple of 64 in k (2 bytes each)
+    assert L.lp_gemm_packed_workspace_bytes(300, 10, 96) == 512 * 128 * 2 + 256 * 128 * 2

@@ -38,7 +38,8 @@ def host(t):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("M,N,K", [(16, 16, 32), (1, 1, 1), (130, 70, 33), (300, 257, 64),
-                                   (1000, 1000, 256), (2050, 130, 512)])
+                                   (1000, 1000, 256), (2050, 130, 512), (384, 256, 96),
+                                   (640, 384, 1024)])
 def test_gemm_update_low_precision(lp, prec, M, N, K):
     rng = np.random.default_rng(M + 3 * N + 7 * K)
     A = rng.uniform(-1, 1, (M, K)).astype(np.float32)
@@ -52,6 +53,32 @@ def test_gemm_update_low_precision(lp, prec, M, N, K):
     bound = (K + 2) * U32 * (np.abs(C) + np.abs(Ar) @ np.abs(Br)) + 1e-30
     err = np.abs(host(tC).astype(np.float64) - ref)
     assert np.all(err <= bound), float(np.max(err / bound))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (256, 256, 64), (300, 257, 64), (513, 700, 96),
+                                   (1000, 1000, 512), (2050, 130, 1024), (700, 2300, 33)])
+def test_gemm_update_packed(lp, prec, M, N, K):
+    """Packed -A / B^T operands on 256 x 256 tiles: ragged tiles, k padded to a
+    power-of-two multiple of 64, strided C; same bound as the unpacked update."""
+    rng = np.random.default_rng(M + 5 * N + 11 * K)
+    A = rng.uniform(-1, 1, (M, K + 3)).astype(np.float32)[:, :K]
+    B = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+    Cfull = rng.uniform(-1, 1, (M, N + 5)).astype(np.float32)
+    tA = cuda(np.ascontiguousarray(rng.uniform(-1, 1, (M, K + 3)).astype(np.float32)))
+    tA[:, :K] = cuda(A)
+    tCf = cuda(Cfull)
+    tC = tCf[:, :N]
+    lp.gemm_update_packed(tC, tA[:, :K], cuda(B), prec=prec)
+    Ar = ir.round_to(A, prec).astype(np.float64)
+    Br = ir.round_to(B, prec).astype(np.float64)
+    C = Cfull[:, :N]
+    ref = C.astype(np.float64) - Ar @ Br
+    bound = (K + 2) * U32 * (np.abs(C) + np.abs(Ar) @ np.abs(Br)) + 1e-30
+    out = host(tCf)
+    err = np.abs(out[:, :N].astype(np.float64) - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    assert np.array_equal(out[:, N:], Cfull[:, N:])  # columns past N untouched
 
 
 @pytest.mark.parametrize("n,nb", [(64, 32), (300, 64), (1000, 128), (2048, 256)])
@@ -88,6 +115,21 @@ def test_refinement_shifted_matrix(lp, prec):
     assert np.all(res[:, 0] < 16)
     # inputs untouched
     assert np.array_equal(host(tA), A) and np.array_equal(host(tB), B)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_refinement_packed_trailing_updates(lp, prec):
+    # n = 6144, nb = 256: the trailing updates right of the next panel run on
+    # packed 256 x 256 tiles (with a ragged last tile row and column)
+    n, nb = 6144 + 40, 256
+    A = inputs.matrix(31, n, shift=float(n))
+    B = inputs.rhs(31, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, prec)
+    r = rep.as_dict()
+    assert r["converged"] == 1 and r["fell_back"] == 0 and r["iterations"] <= 6, r
+    x_o = oracle.solve(A, B)
+    assert np.max(np.abs(host(X) - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    assert np.all(oracle.residual(A, host(X), B)[:, 0] < 16)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

@@ -42,8 +42,13 @@ namespace {
 constexpr int kLW = 32;          // the widest leaf (leaf width LW is 16 or 32)
 constexpr int kChunk = 256;      // rows per thread-sweep (one per thread); RPT chunks per workgroup
 constexpr int kMaxEnt = 2 * kLW;  // gather entries of one leaf's exchanges
+constexpr int kXb = 8;            // exchange elements in flight per thread (binary32; 4 for binary64)
 constexpr int kMaxG = 256;        // workgroups per panel launch
-constexpr int kKeySlots = 1024 * kMaxG;  // one key per (column, workgroup)
+// one key per (column, workgroup), workgroup-major with a padded stride so
+// that the keys of one column, which every workgroup polls, fall on many
+// memory channels
+constexpr int kKeyStride = 1024 + 32;
+constexpr int kKeySlots = kKeyStride * kMaxG;
 
 // Calls f(std::integral_constant<int, J>) for J = J0 .. N-1 in order while it
 // returns true; the index is a compile-time constant inside f.
@@ -70,6 +75,9 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     unsigned long long* __restrict__ keys, unsigned long long* __restrict__ keys_next) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc acc_t;
+  // row blocks of 16 per load batch in (F): a whole 256-row chunk for binary32
+  // rows held one per thread; 8 where registers are tighter
+  constexpr int kRbb = (RPT == 1 && sizeof(T) == 4) ? 16 : 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* stage = reinterpret_cast<T*>(smem_raw);  // [LW][kChunk] column-major, one row chunk
   __shared__ T lblk[kLW * (kLW + 1)];         // the leaf's own rows (diagonal block), row-major
@@ -87,6 +95,8 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   __shared__ int pl_dst[kMaxEnt];
   __shared__ int pl_src[kMaxEnt];
   __shared__ int pl_n;
+  __shared__ int pl_own[kMaxEnt];
+  __shared__ int pl_nown;
   __shared__ unsigned long long red_enc[4];
   __shared__ int red_g[4];
   __shared__ int s_timeout;
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   // than this one, so every key slot of those columns is cleared
   if (G > 1) {  // a single-workgroup launch is followed by single-workgroup launches
     for (int e = g * blockDim.x + tid; e < W * kMaxG; e += G * blockDim.x)
-      xstore(&keys_next[e], 0ull);
+      xstore(&keys_next[(size_t)(e / W) * kKeyStride + e % W], 0ull);
   }
   // the panel is the critical path while the trailing update runs beside it
   // on the same compute units: its waves issue first
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           char* sb = slots + (size_t)par * lay.buf_bytes;
           unsigned long long* recs = reinterpret_cast<unsigned long long*>(sb + lay.rec_off);
           unsigned long long* drec = reinterpret_cast<unsigned long long*>(sb + lay.drec_off);
-          unsigned long long* ckeys = keys + (size_t)(dg - c0) * kMaxG;
+          unsigned long long* ckeys = keys + (size_t)(dg - c0);  // stride kKeyStride
           constexpr int kWPV = (int)(sizeof(T) / 4);  // 32-bit words per value
           constexpr int kIdxW = 2 * kLeafMax;         // index / flag word
           const int nw = kWPV * wb;
@@ -252,7 +262,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             unsigned long long ek = 1ull;  // no candidate
             if (bi != INT_MAX)
               ek = (bk < 0.0) ? 2ull : 3ull + (unsigned long long)__double_as_longlong(bk);
-            xstore(&ckeys[g], ek);
+            xstore(&ckeys[(size_t)g * kKeyStride], ek);
           }
           // wait for every workgroup's key; the largest wins, the lowest
           // workgroup (hence the lowest row) on ties
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           int kg = INT_MAX;
           if (tid < G) {
             const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-            while ((kv = xload(&ckeys[tid])) == 0ull) {
+            while ((kv = xload(&ckeys[(size_t)tid * kKeyStride])) == 0ull) {
               __builtin_amdgcn_s_sleep(1);
               if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
                 s_timeout = 1;
@@ -405,28 +415,53 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     const int nout = W - wb;
     const int nleft = cb - c0;
     if (nout > 0 && nent > 0) {
-      for (int e2 = tid; e2 < nent * nout; e2 += blockDim.x) {
-        const int e = e2 / nout;
-        const int ci = e2 - e * nout;
-        const int d = pl_dst[e];
-        if ((d - c0) / R == g) {
-          const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
-          xstore(&staging[(long long)e * W + ci], xload(&A[(long long)pl_src[e] * lda + col]));
-        }
+      // this workgroup's destinations, compacted by the first wave
+      if (wave == 0) {
+        const bool own = lane < nent && (pl_dst[lane] - c0) / R == g;
+        const unsigned long long mask = __ballot(own);
+        if (own) pl_own[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+        if (lane == 0) pl_nown = __popcll(mask);
       }
+      __syncthreads();
+      const int tot = pl_nown * nout;
+      // every load of a round is issued before its stores: one fabric round
+      // trip per kXb elements per thread
+      auto move = [&](bool gather) {
+        constexpr int XB = sizeof(T) == 4 ? kXb : kXb / 2;
+        for (int e0 = tid; e0 < tot; e0 += XB * 256) {
+          T v[XB];
+#pragma unroll
+          for (int u = 0; u < XB; ++u) {
+            const int e2 = e0 + u * 256;
+            if (e2 < tot) {
+              const int e = pl_own[e2 / nout];
+              const int ci = e2 % nout;
+              const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
+              v[u] = gather ? xload(&A[(long long)pl_src[e] * lda + col])
+                            : xload(&staging[(long long)e * W + ci]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < XB; ++u) {
+            const int e2 = e0 + u * 256;
+            if (e2 < tot) {
+              const int e = pl_own[e2 / nout];
+              const int ci = e2 % nout;
+              const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
+              if (gather)
+                xstore(&staging[(long long)e * W + ci], v[u]);
+              else
+                xstore(&A[(long long)pl_dst[e] * lda + col], v[u]);
+            }
+          }
+        }
+      };
+      move(true);
       if (!sync_all()) {
         if (g == 0 && tid == 0) *info = LP_INFO_BARRIER_TIMEOUT;
         return;
       }
-      for (int e2 = tid; e2 < nent * nout; e2 += blockDim.x) {
-        const int e = e2 / nout;
-        const int ci = e2 - e * nout;
-        const int d = pl_dst[e];
-        if ((d - c0) / R == g) {
-          const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
-          xstore(&A[(long long)d * lda + col], xload(&staging[(long long)e * W + ci]));
-        }
-      }
+      move(false);
     }
     if (nright <= 0) {
       wg_sync();
@@ -487,10 +522,12 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             const int k = 16 * s2 + MF::kidx(gq, t);
             bfr[s2][t] = (k < wb && colok) ? xload(&A[(long long)(cb + k) * lda + col]) : T(0);
           }
-        for (int rg = 0; rg < nrb; rg += 4) {
-          acc_t acc[4];
+        // all row blocks of a batch are loaded before the first product, so a
+        // batch costs one round trip to memory
+        for (int rg = 0; rg < nrb; rg += kRbb) {
+          acc_t acc[kRbb];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < kRbb; ++u) {
             const int rloc = r0 + rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -500,9 +537,10 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             }
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < kRbb; ++u) {
+            if (rg + u >= nrb) continue;
             const int arow = rb0 + 16 * (rg + u) + l16;  // chunk-relative
-            const bool rowok = (rg + u < nrb) && arow < kChunk;
+            const bool rowok = arow < kChunk;
 #pragma unroll
             for (int s2 = 0; s2 < LW / 16; ++s2)
 #pragma unroll
@@ -513,7 +551,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
               }
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < kRbb; ++u) {
             const int rloc = r0 + rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {

@@ -302,6 +302,18 @@ bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
   return false;
 }
 
+// Workgroups of a binary64 panel that runs beside the trailing update: 64 of
+// up to 1024 rows each leave the other compute units to the update's FP64
+// MFMAs, which on one MI355X shortened the whole factorization (n = 32768 and
+// 65536) although such a panel alone is slower than one spread over every
+// compute unit.  Binary32 panels are the longer chain of the low-precision
+// factorization and keep one workgroup per 256 rows (0: the default spread).
+template <typename T>
+int lookahead_panel_wgs(int rows) {
+  if (sizeof(T) != 8) return 0;
+  return std::max(64, (int)cdiv(rows, kPanelRowsPerWg));
+}
+
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
                 char* work, hipStream_t s, const FactorCfg& cfg, Prof& prof) {
@@ -448,7 +460,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       LP_HIP_TRY(hipStreamWaitEvent(ps, next_ready, 0));
       f.s = ps;
       if ((rc = prof.begin(prof.panel, ps)) != LP_OK) return rc;
-      if ((rc = f.panel(j1, w2, pwgs)) != LP_OK) return rc;
+      if ((rc = f.panel(j1, w2, pwgs ? pwgs : lookahead_panel_wgs<T>(n - j1))) != LP_OK) return rc;
       if ((rc = prof.end(prof.panel, ps)) != LP_OK) return rc;
       f.s = s;
       if ((rc = la.event(&panel_done)) != LP_OK) return rc;

@@ -42,6 +42,7 @@ namespace {
 constexpr int kLW = 32;          // the widest leaf (leaf width LW is 16 or 32)
 constexpr int kChunk = 256;      // rows per thread-sweep (one per thread); RPT chunks per workgroup
 constexpr int kMaxEnt = 2 * kLW;  // gather entries of one leaf's exchanges
+constexpr int kLd = 8;            // leaf-load elements in flight per thread
 constexpr int kXb = 8;            // exchange elements in flight per thread (binary32; 4 for binary64)
 constexpr int kMaxG = 256;        // workgroups per panel launch
 // one key per (column, workgroup), workgroup-major with a padded stride so
@@ -150,10 +151,25 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     for (int q = 0; q < RPT; ++q) {
       const int r0 = kChunk * q;
       const int lo = max(rlo, r0), hi = min(nrows, r0 + kChunk);
-      for (int e = (lo - r0) * wb + tid; e < (hi - r0) * wb; e += blockDim.x) {
-        const int r = e / wb;
-        const int c = e - r * wb;
-        stage[c * kChunk + r] = xload(&A[(long long)(base + r0 + r) * lda + cb + c]);
+      // kLd loads in flight per thread; out-of-range slots load a valid
+      // element and drop it (a load under a branch would wait in the branch)
+      const int e_lo = (lo - r0) * wb, e_hi = (hi - r0) * wb;
+      for (int e0 = e_lo + tid; e0 < e_hi; e0 += kLd * 256) {
+        T v[kLd];
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+          const int e = min(e0 + u * 256, e_hi - 1);
+          const int r = e / wb;
+          v[u] = xload(&A[(long long)(base + r0 + r) * lda + cb + (e - r * wb)]);
+        }
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+          const int e = e0 + u * 256;
+          if (e < e_hi) {
+            const int r = e / wb;
+            stage[(e - r * wb) * kChunk + r] = v[u];
+          }
+        }
       }
       __syncthreads();
       const int r = r0 + tid;
@@ -432,14 +448,12 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           T v[XB];
 #pragma unroll
           for (int u = 0; u < XB; ++u) {
-            const int e2 = e0 + u * 256;
-            if (e2 < tot) {
-              const int e = pl_own[e2 / nout];
-              const int ci = e2 % nout;
-              const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
-              v[u] = gather ? xload(&A[(long long)pl_src[e] * lda + col])
-                            : xload(&staging[(long long)e * W + ci]);
-            }
+            const int e2 = min(e0 + u * 256, tot - 1);
+            const int e = pl_own[e2 / nout];
+            const int ci = e2 % nout;
+            const int col = (ci < nleft) ? c0 + ci : ci + wb + c0;
+            v[u] = gather ? xload(&A[(long long)pl_src[e] * lda + col])
+                          : xload(&staging[(long long)e * W + ci]);
           }
 #pragma unroll
           for (int u = 0; u < XB; ++u) {
@@ -475,7 +489,10 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
         T x[LW];
 #pragma unroll
         for (int i = 0; i < LW; ++i)
-          x[i] = (i < wb) ? xload(&A[(long long)(cb + i) * lda + right0 + col]) : T(0);
+          x[i] = xload(&A[(long long)(cb + min(i, wb - 1)) * lda + right0 + col]);
+#pragma unroll
+        for (int i = 0; i < LW; ++i)
+          if (i >= wb) x[i] = T(0);
 #pragma unroll
         for (int i = 1; i < LW; ++i) {
           if (i < wb) {
@@ -520,7 +537,9 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int k = 16 * s2 + MF::kidx(gq, t);
-            bfr[s2][t] = (k < wb && colok) ? xload(&A[(long long)(cb + k) * lda + col]) : T(0);
+            const bool ok = k < wb && colok;
+            const T raw = xload(&A[ok ? (long long)(cb + k) * lda + col : (long long)cb * lda + c0]);
+            bfr[s2][t] = ok ? raw : T(0);
           }
         // all row blocks of a batch are loaded before the first product, so a
         // batch costs one round trip to memory
@@ -533,7 +552,9 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             for (int v = 0; v < 4; ++v) {
               const int row = rloc + MF::drow(gq, v);
               const bool ok = (rg + u < nrb) && row >= lo && row < hi && colok;
-              acc[u][v] = ok ? -xload(&A[(long long)(base + row) * lda + col]) : T(0);
+              const T raw =
+                  xload(&A[ok ? (long long)(base + row) * lda + col : (long long)base * lda + c0]);
+              acc[u][v] = ok ? -raw : T(0);
             }
           }
 #pragma unroll
@@ -541,14 +562,21 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             if (rg + u >= nrb) continue;
             const int arow = rb0 + 16 * (rg + u) + l16;  // chunk-relative
             const bool rowok = arow < kChunk;
+            // the row block's L values first, then its products
+            T av[LW / 16][4];
 #pragma unroll
             for (int s2 = 0; s2 < LW / 16; ++s2)
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const int k = 16 * s2 + MF::kidx(gq, t);
-                const T a = (rowok && k < wb) ? stage[k * kChunk + arow] : T(0);
-                acc[u] = MF::mma(a, bfr[s2][t], acc[u]);
+                const bool ok = rowok && k < wb;
+                const T a0 = stage[ok ? k * kChunk + arow : 0];
+                av[s2][t] = ok ? a0 : T(0);
               }
+#pragma unroll
+            for (int s2 = 0; s2 < LW / 16; ++s2)
+#pragma unroll
+              for (int t = 0; t < 4; ++t) acc[u] = MF::mma(av[s2][t], bfr[s2][t], acc[u]);
           }
 #pragma unroll
           for (int u = 0; u < kRbb; ++u) {

@@ -5,9 +5,9 @@
 // Right-hand sides are row-major n x nrhs.  The interchanges recorded by the
 // factorization are applied to B first, in chunks of up to 1024 swaps with the
 // same parallel swap plan the factorization uses.  Each triangle is then
-// solved block by block (128 rows): one workgroup solves the diagonal block
-// with the block held in LDS, and a grid of threads (one per row) subtracts
-// that block's contribution from all later rows.
+// solved block by block (128 rows): one wave per right-hand side solves the
+// diagonal block with the block held in LDS, and a grid of threads (one per
+// row) subtracts that block's contribution from all later rows.
 #include <cmath>
 
 #include "common.h"
@@ -68,15 +68,28 @@ __global__ __launch_bounds__(1024) void permute_rows_kernel(int n, const int32_t
 // ------------------------------------------------- diagonal-block solves
 // lower == true: unit lower forward substitution on rows [r0, r0 + bs).
 // lower == false: upper back substitution (divides by the diagonal).
-// Thread (i, c) = (tid / 8, tid % 8) holds b[r0 + i][c0 + c].
+// One wave per right-hand side of a chunk; lane l holds rows l and l + 64 of
+// the block.  Step j takes row j's value from the lane that holds it (a
+// register read across lanes, no barrier) and every lane updates its rows with
+// the block's factors from LDS.
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned)lo);
+  }
+}
+
 template <typename T, bool lower>
-__global__ __launch_bounds__(1024) void trsv_diag_kernel(int n, int r0, const T* __restrict__ LU,
-                                                         long long lda, T* __restrict__ B,
-                                                         long long ldb, int nrhs,
-                                                         const int32_t* __restrict__ info) {
+__global__ __launch_bounds__(64 * kRhsChunk) void trsv_diag_kernel(
+    int n, int r0, const T* __restrict__ LU, long long lda, T* __restrict__ B, long long ldb,
+    int nrhs, const int32_t* __restrict__ info) {
   if (info != nullptr && *info != 0) return;
   __shared__ T Ls[kTB][kTB + 1];
-  __shared__ T yv[kTB][kRhsChunk];
   const int bs = min(kTB, n - r0);
   for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
     const int i = e / bs;
@@ -84,34 +97,38 @@ __global__ __launch_bounds__(1024) void trsv_diag_kernel(int n, int r0, const T*
     Ls[i][j] = LU[(long long)(r0 + i) * lda + r0 + j];
   }
   __syncthreads();
-  const int i = threadIdx.x >> 3;
-  const int c = threadIdx.x & 7;
-  for (int c0 = 0; c0 < nrhs; c0 += kRhsChunk) {
-    const bool act = (i < bs) && (c0 + c < nrhs);
-    T b = act ? B[(long long)(r0 + i) * ldb + c0 + c] : T(0);
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int i0 = lane, i1 = lane + 64;
+  // rows past the block read a valid LDS row; their values are never stored
+  const int l0 = min(i0, bs - 1), l1 = min(i1, bs - 1);
+  for (int c = w; c < nrhs; c += kRhsChunk) {
+    T b0 = (i0 < bs) ? B[(long long)(r0 + i0) * ldb + c] : T(0);
+    T b1 = (i1 < bs) ? B[(long long)(r0 + i1) * ldb + c] : T(0);
     if (lower) {
       for (int j = 0; j < bs; ++j) {
-        if (i == j) yv[j][c] = b;
-        __syncthreads();
-        if (i > j) b -= Ls[i][j] * yv[j][c];
+        const T yj = lane_value(j < 64 ? b0 : b1, j & 63);
+        if (i0 > j) b0 -= Ls[l0][j] * yj;
+        if (i1 > j) b1 -= Ls[l1][j] * yj;
       }
     } else {
       for (int j = bs - 1; j >= 0; --j) {
-        if (i == j) {
-          b = b / Ls[j][j];
-          yv[j][c] = b;
-        }
-        __syncthreads();
-        if (i < j) b -= Ls[i][j] * yv[j][c];
+        const T yj = lane_value(j < 64 ? b0 : b1, j & 63) / Ls[j][j];
+        if (i0 == j) b0 = yj;
+        if (i1 == j) b1 = yj;
+        if (i0 < j) b0 -= Ls[l0][j] * yj;
+        if (i1 < j) b1 -= Ls[l1][j] * yj;
       }
     }
-    if (act) B[(long long)(r0 + i) * ldb + c0 + c] = b;
-    __syncthreads();
+    if (i0 < bs) B[(long long)(r0 + i0) * ldb + c] = b0;
+    if (i1 < bs) B[(long long)(r0 + i1) * ldb + c] = b1;
   }
 }
 
-// rows [rb, re) of B -= LU[rows, r0 : r0 + bs] * B[r0 : r0 + bs, :]
-template <typename T>
+// rows [rb, re) of B -= LU[rows, r0 : r0 + bs] * B[r0 : r0 + bs, :]; with VEC
+// each thread reads its row of the factors 16 bytes at a time (bs a multiple
+// of the vector width, rows 16-byte aligned)
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void trsv_update_kernel(int rb, int re, int r0, int bs,
                                                           const T* __restrict__ LU, long long lda,
                                                           T* __restrict__ B, long long ldb,
@@ -119,6 +136,8 @@ __global__ __launch_bounds__(256) void trsv_update_kernel(int rb, int re, int r0
                                                           const int32_t* __restrict__ info) {
   if (info != nullptr && *info != 0) return;
   __shared__ T ys[kTB][kRhsChunk];
+  constexpr int E = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(E)));
   const int i = rb + blockIdx.x * blockDim.x + threadIdx.x;
   for (int c0 = 0; c0 < nrhs; c0 += kRhsChunk) {
     const int cw = min(kRhsChunk, nrhs - c0);
@@ -133,10 +152,30 @@ __global__ __launch_bounds__(256) void trsv_update_kernel(int rb, int re, int r0
 #pragma unroll
       for (int c = 0; c < kRhsChunk; ++c) acc[c] = T(0);
       const T* row = LU + (long long)i * lda + r0;
-      for (int k = 0; k < bs; ++k) {
-        const T l = row[k];
+      if constexpr (VEC) {
+        for (int k0 = 0; k0 < bs; k0 += 4 * E) {
+          vec_t v[4];
 #pragma unroll
-        for (int c = 0; c < kRhsChunk; ++c) acc[c] += l * ys[k][c];
+          for (int u = 0; u < 4; ++u)
+            v[u] = (k0 + u * E < bs) ? *reinterpret_cast<const vec_t*>(row + k0 + u * E)
+                                     : vec_t(T(0));
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (k0 + u * E >= bs) break;  // the same for every thread
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const int k = k0 + u * E + e;
+#pragma unroll
+              for (int c = 0; c < kRhsChunk; ++c) acc[c] += v[u][e] * ys[k][c];
+            }
+          }
+        }
+      } else {
+        for (int k = 0; k < bs; ++k) {
+          const T l = row[k];
+#pragma unroll
+          for (int c = 0; c < kRhsChunk; ++c) acc[c] += l * ys[k][c];
+        }
       }
       for (int c = 0; c < cw; ++c) B[(long long)i * ldb + c0 + c] -= acc[c];
     }
@@ -253,28 +292,40 @@ int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, cons
                      info);
   LP_LAUNCH_CHECK();
   const int nblk = (int)cdiv(n, kTB);
+  // 16-byte row reads of the factors: rows aligned (block offsets are
+  // multiples of kTB, a multiple of the vector width)
+  const int vw = 16 / (int)sizeof(T);
+  const bool vec = ((uintptr_t)LU % 16 == 0) && ((lda * (long long)sizeof(T)) % 16 == 0);
   for (int b = 0; b < nblk; ++b) {
     const int r0 = b * kTB;
     const int bs = min(kTB, n - r0);
-    hipLaunchKernelGGL((trsv_diag_kernel<T, true>), dim3(1), dim3(1024), 0, s, n, r0, LU, lda, B,
-                       ldb, nrhs, info);
+    hipLaunchKernelGGL((trsv_diag_kernel<T, true>), dim3(1), dim3(64 * kRhsChunk), 0, s, n, r0,
+                       LU, lda, B, ldb, nrhs, info);
     LP_LAUNCH_CHECK();
     const int rb = r0 + bs;
     if (rb < n) {
-      hipLaunchKernelGGL((trsv_update_kernel<T>), dim3((unsigned)cdiv(n - rb, 256)), dim3(256), 0,
-                         s, rb, n, r0, bs, LU, lda, B, ldb, nrhs, info);
+      if (vec && bs % vw == 0)
+        hipLaunchKernelGGL((trsv_update_kernel<T, true>), dim3((unsigned)cdiv(n - rb, 256)),
+                           dim3(256), 0, s, rb, n, r0, bs, LU, lda, B, ldb, nrhs, info);
+      else
+        hipLaunchKernelGGL((trsv_update_kernel<T, false>), dim3((unsigned)cdiv(n - rb, 256)),
+                           dim3(256), 0, s, rb, n, r0, bs, LU, lda, B, ldb, nrhs, info);
       LP_LAUNCH_CHECK();
     }
   }
   for (int b = nblk - 1; b >= 0; --b) {
     const int r0 = b * kTB;
     const int bs = min(kTB, n - r0);
-    hipLaunchKernelGGL((trsv_diag_kernel<T, false>), dim3(1), dim3(1024), 0, s, n, r0, LU, lda,
-                       B, ldb, nrhs, info);
+    hipLaunchKernelGGL((trsv_diag_kernel<T, false>), dim3(1), dim3(64 * kRhsChunk), 0, s, n, r0,
+                       LU, lda, B, ldb, nrhs, info);
     LP_LAUNCH_CHECK();
     if (r0 > 0) {
-      hipLaunchKernelGGL((trsv_update_kernel<T>), dim3((unsigned)cdiv(r0, 256)), dim3(256), 0, s,
-                         0, r0, r0, bs, LU, lda, B, ldb, nrhs, info);
+      if (vec && bs % vw == 0)
+        hipLaunchKernelGGL((trsv_update_kernel<T, true>), dim3((unsigned)cdiv(r0, 256)),
+                           dim3(256), 0, s, 0, r0, r0, bs, LU, lda, B, ldb, nrhs, info);
+      else
+        hipLaunchKernelGGL((trsv_update_kernel<T, false>), dim3((unsigned)cdiv(r0, 256)),
+                           dim3(256), 0, s, 0, r0, r0, bs, LU, lda, B, ldb, nrhs, info);
       LP_LAUNCH_CHECK();
     }
   }

@@ -185,6 +185,21 @@ def test_lu_factor_solve_matches_oracle(lp, n, nb):
     assert np.all(res[:, 0] < 16)
 
 
+@pytest.mark.parametrize("n,nrhs", [(700, 11), (640, 17), (901, 9)])
+def test_solve_many_right_hand_sides(lp, n, nrhs):
+    """More right-hand sides than one pass of the triangular solves takes (8),
+    with and without 16-byte-aligned rows of the factors."""
+    A = inputs.matrix(5 + n, n)
+    B = inputs.rhs(5 + n, n, nrhs)
+    tA, ipiv, info, tB, st = factor_and_solve(lp, A, B, 64)
+    lu_o, piv_o, _ = oracle.getrf(A)
+    x_o = oracle.getrs(lu_o, piv_o, B)
+    assert int(host(st)[0]) == 0
+    x = host(tB)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    assert np.all(oracle.residual(A, x, B)[:, 0] < 16)
+
+
 @pytest.mark.parametrize("n,nb", [(4096, 256), (9000, 128)])
 def test_reserved_panel_units_match_oracle(lp, n, nb):
     """Every panel after the first on 32 reserved compute units (1024-row

@@ -91,10 +91,26 @@ __global__ __launch_bounds__(64 * kRhsChunk) void trsv_diag_kernel(
   if (info != nullptr && *info != 0) return;
   __shared__ T Ls[kTB][kTB + 1];
   const int bs = min(kTB, n - r0);
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const int i = e / bs;
-    const int j = e - i * bs;
-    Ls[i][j] = LU[(long long)(r0 + i) * lda + r0 + j];
+  // the block into LDS with 16 loads in flight per thread (a loop that stores
+  // each load before issuing the next pays one memory latency per element)
+  constexpr int kB = 16;
+  const int nel = bs * bs;
+  for (int e0 = threadIdx.x; e0 < nel; e0 += kB * (int)blockDim.x) {
+    T v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = min(e0 + u * (int)blockDim.x, nel - 1);
+      const int i = e / bs;
+      v[u] = LU[(long long)(r0 + i) * lda + r0 + (e - i * bs)];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < nel) {
+        const int i = e / bs;
+        Ls[i][e - i * bs] = v[u];
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -105,19 +121,36 @@ __global__ __launch_bounds__(64 * kRhsChunk) void trsv_diag_kernel(
   for (int c = w; c < nrhs; c += kRhsChunk) {
     T b0 = (i0 < bs) ? B[(long long)(r0 + i0) * ldb + c] : T(0);
     T b1 = (i1 < bs) ? B[(long long)(r0 + i1) * ldb + c] : T(0);
+    // factors are read unconditionally and the row conditions select
+    // afterwards; full blocks unroll the steps so that the LDS reads of later
+    // steps are issued ahead of the chain through the broadcast values
+    auto fwd = [&](int j) {
+      const T a0 = Ls[l0][j], a1 = Ls[l1][j];
+      const T yj = lane_value(j < 64 ? b0 : b1, j & 63);
+      const T n0 = b0 - a0 * yj, n1 = b1 - a1 * yj;
+      b0 = (i0 > j) ? n0 : b0;
+      b1 = (i1 > j) ? n1 : b1;
+    };
+    auto bwd = [&](int j) {
+      const T a0 = Ls[l0][j], a1 = Ls[l1][j], d = Ls[j][j];
+      const T yj = lane_value(j < 64 ? b0 : b1, j & 63) / d;
+      const T n0 = b0 - a0 * yj, n1 = b1 - a1 * yj;
+      b0 = (i0 == j) ? yj : ((i0 < j) ? n0 : b0);
+      b1 = (i1 == j) ? yj : ((i1 < j) ? n1 : b1);
+    };
     if (lower) {
-      for (int j = 0; j < bs; ++j) {
-        const T yj = lane_value(j < 64 ? b0 : b1, j & 63);
-        if (i0 > j) b0 -= Ls[l0][j] * yj;
-        if (i1 > j) b1 -= Ls[l1][j] * yj;
+      if (bs == kTB) {
+#pragma unroll
+        for (int j = 0; j < kTB; ++j) fwd(j);
+      } else {
+        for (int j = 0; j < bs; ++j) fwd(j);
       }
     } else {
-      for (int j = bs - 1; j >= 0; --j) {
-        const T yj = lane_value(j < 64 ? b0 : b1, j & 63) / Ls[j][j];
-        if (i0 == j) b0 = yj;
-        if (i1 == j) b1 = yj;
-        if (i0 < j) b0 -= Ls[l0][j] * yj;
-        if (i1 < j) b1 -= Ls[l1][j] * yj;
+      if (bs == kTB) {
+#pragma unroll
+        for (int j = kTB - 1; j >= 0; --j) bwd(j);
+      } else {
+        for (int j = bs - 1; j >= 0; --j) bwd(j);
       }
     }
     if (i0 < bs) B[(long long)(r0 + i0) * ldb + c] = b0;
@@ -141,10 +174,22 @@ __global__ __launch_bounds__(256) void trsv_update_kernel(int rb, int re, int r0
   const int i = rb + blockIdx.x * blockDim.x + threadIdx.x;
   for (int c0 = 0; c0 < nrhs; c0 += kRhsChunk) {
     const int cw = min(kRhsChunk, nrhs - c0);
-    for (int e = threadIdx.x; e < bs * kRhsChunk; e += blockDim.x) {
-      const int k = e >> 3;
-      const int c = e & 7;
-      ys[k][c] = (c < cw) ? B[(long long)(r0 + k) * ldb + c0 + c] : T(0);
+    {
+      // kTB * kRhsChunk / 256 = 4 entries per thread, all loads first
+      constexpr int kY = kTB * kRhsChunk / 256;
+      T v[kY];
+#pragma unroll
+      for (int u = 0; u < kY; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int k = min(e >> 3, bs - 1), c = min(e & 7, cw - 1);
+        v[u] = B[(long long)(r0 + k) * ldb + c0 + c];
+      }
+#pragma unroll
+      for (int u = 0; u < kY; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int k = e >> 3, c = e & 7;
+        if (k < bs) ys[k][c] = (c < cw) ? v[u] : T(0);
+      }
     }
     __syncthreads();
     if (i < re) {

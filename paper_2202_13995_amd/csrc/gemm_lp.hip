@@ -16,10 +16,18 @@
 //   operands as one 16-byte run from LDS.  The B tile is stored transposed
 //   (column-major in k) for the same reason.
 //
-// A workgroup (4 waves) owns a 128 x 128 tile of C, wave w the 64 x 64 quadrant
-// (w / 2, w % 2) as 4 x 4 fragments; K advances in slabs through two LDS
-// buffers (one barrier per slab); accumulators start at -C and the tile is
-// written back negated.  Tiles are numbered XCD-aware as in the FP64 kernel.
+// Three kernels share these conventions:
+//   sgemm_update_body / sgemm_update_kernel: any tile, any K.  A workgroup
+//     (4 waves) owns a 128 x 128 tile of C, wave w the 64 x 64 quadrant
+//     (w / 2, w % 2) as 4 x 4 fragments; K advances in slabs through two LDS
+//     buffers (one barrier per slab); accumulators start at -C and the tile is
+//     written back negated.
+//   sgemm_update_fast: interior 128 x 128 tiles for bfloat16 / half with
+//     K = 64 NK, binary32 operands narrowed into LDS (A negated there),
+//     accumulators started at C.
+//   hgemm_update_packed: operands packed once per block step as 16-bit -A and
+//     B^T, 256 x 256 tiles on 8 waves (the factorization's large updates).
+// Tiles are numbered XCD-aware as in the FP64 kernel.
 #include <type_traits>
 
 #include "common.h"

@@ -59,6 +59,50 @@ __device__ __forceinline__ bool better(double ka, int ia, double kb, int ib) {
   return ka > kb || (ka == kb && ia < ib);
 }
 
+// The best (key, index) pair of a wave, in every lane: four DPP exchanges
+// inside each row of 16 lanes (quad swaps, then half-row and row mirrors,
+// each pairing a lane with one from the other half), then the four rows'
+// winners read across lanes.  `first(a, ia, b, ib)` must be a strict order
+// (as `better` is), so the result does not depend on the reduction's shape.
+// Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_move(unsigned v) {
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename F>
+__device__ __forceinline__ void wave_best_step(unsigned long long& key, int& idx, F& first) {
+  const unsigned lo = dpp_move<CTRL>((unsigned)key);
+  const unsigned hi = dpp_move<CTRL>((unsigned)(key >> 32));
+  const int oi = (int)dpp_move<CTRL>((unsigned)idx);
+  const unsigned long long ok = ((unsigned long long)hi << 32) | lo;
+  if (first(ok, oi, key, idx)) {
+    key = ok;
+    idx = oi;
+  }
+}
+template <typename F>
+__device__ __forceinline__ void wave_best(unsigned long long& key, int& idx, F first) {
+  wave_best_step<0xB1>(key, idx, first);   // quad_perm [1, 0, 3, 2]
+  wave_best_step<0x4E>(key, idx, first);   // quad_perm [2, 3, 0, 1]
+  wave_best_step<0x141>(key, idx, first);  // row_half_mirror
+  wave_best_step<0x140>(key, idx, first);  // row_mirror
+  unsigned long long bk = 0;
+  int bi = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)key, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(key >> 32), 16 * r);
+    const int ri = __builtin_amdgcn_readlane(idx, 16 * r);
+    const unsigned long long rk = ((unsigned long long)hi << 32) | lo;
+    if (r == 0 || first(rk, ri, bk, bi)) {
+      bk = rk;
+      bi = ri;
+    }
+  }
+  key = bk;
+  idx = bi;
+}
+
 template <typename T>
 struct Mfma16;
 

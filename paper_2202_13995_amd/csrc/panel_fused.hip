@@ -201,14 +201,13 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             }
           }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ok = __shfl_xor(bk, off);
-          const int oi = __shfl_xor(bi, off);
-          if (better(ok, oi, bk, bi)) {
-            bk = ok;
-            bi = oi;
-          }
+        {
+          unsigned long long kb = (unsigned long long)__double_as_longlong(bk);
+          wave_best(kb, bi, [](unsigned long long ka, int ia, unsigned long long kc, int ic) {
+            return better(__longlong_as_double((long long)ka), ia,
+                          __longlong_as_double((long long)kc), ic);
+          });
+          bk = __longlong_as_double((long long)kb);
         }
         // the wave's candidate row and the diagonal row go to LDS
 #pragma unroll
@@ -295,15 +294,9 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
             }
             kg = tid;
           }
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long ov = __shfl_xor(kv, off);
-            const int og = __shfl_xor(kg, off);
-            if (ov > kv || (ov == kv && og < kg)) {
-              kv = ov;
-              kg = og;
-            }
-          }
+          wave_best(kv, kg, [](unsigned long long a, int ia, unsigned long long b, int ib) {
+            return a > b || (a == b && ia < ib);
+          });
           if (lane == 0) {
             red_enc[wave] = kv;
             red_g[wave] = kg;

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "common.h"
+#include "device.h"
 
 namespace lp {
 namespace {
@@ -85,14 +86,13 @@ __device__ int wg_getrf(int n, T* W, int32_t* ipiv, int32_t* perm, double* rk, i
         bi = i;
       }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ok = __shfl_xor(bk, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ok > bk || (ok == bk && oi < bi)) {
-        bk = ok;
-        bi = oi;
-      }
+    {
+      unsigned long long kb = (unsigned long long)__double_as_longlong(bk);
+      wave_best(kb, bi, [](unsigned long long ka, int ia, unsigned long long kc, int ic) {
+        return better(__longlong_as_double((long long)ka), ia,
+                      __longlong_as_double((long long)kc), ic);
+      });
+      bk = __longlong_as_double((long long)kb);
     }
     if ((threadIdx.x & 63) == 0) {
       rk[threadIdx.x >> 6] = bk;

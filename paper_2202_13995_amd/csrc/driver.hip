@@ -302,16 +302,18 @@ bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
   return false;
 }
 
-// Workgroups of a binary64 panel that runs beside the trailing update: 64 of
-// up to 1024 rows each leave the other compute units to the update's FP64
-// MFMAs, which on one MI355X shortened the whole factorization (n = 32768 and
-// 65536) although such a panel alone is slower than one spread over every
-// compute unit.  Binary32 panels are the longer chain of the low-precision
-// factorization and keep one workgroup per 256 rows (0: the default spread).
+// Workgroups of a binary64 panel that runs beside the trailing update: 48 of
+// up to 1024 rows each (more when the rows need them) leave the other compute
+// units to the update's FP64 MFMAs, which on one MI355X shortened the whole
+// factorization (n = 32768 and 65536; 32, 48 and 64 within 4% of each other,
+// 96 or more and one per 256 rows slower) although such a panel alone is
+// slower than one spread over every compute unit.  Binary32 panels are the
+// longer chain of the low-precision factorization and keep one workgroup per
+// 256 rows (0: the default spread).
 template <typename T>
 int lookahead_panel_wgs(int rows) {
   if (sizeof(T) != 8) return 0;
-  return std::max(64, (int)cdiv(rows, kPanelRowsPerWg));
+  return std::max(48, (int)cdiv(rows, kPanelRowsPerWg));
 }
 
 template <typename T>

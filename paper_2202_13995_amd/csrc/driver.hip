@@ -302,18 +302,18 @@ bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
   return false;
 }
 
-// Workgroups of a binary64 panel that runs beside the trailing update: 48 of
-// up to 1024 rows each (more when the rows need them) leave the other compute
-// units to the update's FP64 MFMAs, which on one MI355X shortened the whole
-// factorization (n = 32768 and 65536; 32, 48 and 64 within 4% of each other,
-// 96 or more and one per 256 rows slower) although such a panel alone is
-// slower than one spread over every compute unit.  Binary32 panels are the
-// longer chain of the low-precision factorization and keep one workgroup per
-// 256 rows (0: the default spread).
+// Workgroups of a panel that runs beside the trailing update.  Binary64: 48
+// of up to 1024 rows each (more when the rows need them) leave the other
+// compute units to the update's FP64 MFMAs, which on one MI355X shortened the
+// whole factorization (n = 32768 and 65536; 32, 48 and 64 within 4% of each
+// other, 96 or more and one per 256 rows slower) although such a panel alone
+// is slower than one spread over every compute unit.  Binary32 panels are the
+// longer chain of the low-precision factorization for more of its steps: at
+// most 128 workgroups (512 rows each above 32768 rows) measured best there
+// (n = 65536: 0.94 against 1.00 s with one per 256 rows; 64 everywhere 1.50 s).
 template <typename T>
 int lookahead_panel_wgs(int rows) {
-  if (sizeof(T) != 8) return 0;
-  return std::max(48, (int)cdiv(rows, kPanelRowsPerWg));
+  return std::max(sizeof(T) == 8 ? 48 : 128, (int)cdiv(rows, kPanelRowsPerWg));
 }
 
 template <typename T>

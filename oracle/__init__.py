@@ -49,6 +49,8 @@ def _load():
         lib.orc_getrs.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp, ctypes.c_int,
                                   ctypes.c_int]
         lib.orc_getrs.restype = ctypes.c_int
+        lib.orc_getrs_trans.argtypes = lib.orc_getrs.argtypes
+        lib.orc_getrs_trans.restype = ctypes.c_int
         for name in ("orc_residual", "orc_residual_ld"):
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
@@ -114,8 +116,9 @@ def getrf_nopiv(a):
     return lu, int(info[0])
 
 
-def getrs(lu, ipiv, b):
-    """Solve with factors from getrf. b is n or n x nrhs; returns x (same shape)."""
+def getrs(lu, ipiv, b, trans: bool = False):
+    """Solve with factors from getrf. b is n or n x nrhs; returns x (same shape).
+    trans=True solves A^T x = b with the same factors."""
     lib = _load()
     lu = _as_f64(lu)
     n = lu.shape[0]
@@ -124,7 +127,8 @@ def getrs(lu, ipiv, b):
     bb = np.ascontiguousarray(b.reshape(n, -1))
     nrhs = bb.shape[1]
     piv = None if ipiv is None else np.ascontiguousarray(np.asarray(ipiv, dtype=np.int32))
-    rc = lib.orc_getrs(n, _dp(lu), max(lu.shape[1], 1),
+    f = lib.orc_getrs_trans if trans else lib.orc_getrs
+    rc = f(n, _dp(lu), max(lu.shape[1], 1),
                        _ip(piv) if piv is not None else None, _dp(bb), max(nrhs, 1), nrhs)
     if rc < 0:
         raise ValueError(f"orc_getrs rejected argument {-rc}")

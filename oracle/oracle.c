@@ -194,6 +194,55 @@ int orc_getrs(int n, const double *LU, int lda, const int *ipiv, double *B, int 
   return 0;
 }
 
+/* Solve A^T X = B with the factors of orc_getrf (P A = L U, so
+ * A^T = U^T L^T P): U^T z = b by forward substitution (U^T is lower, with
+ * the u_ii on its diagonal), L^T w = z by back substitution (unit upper),
+ * then x = P^T w, i.e. the recorded interchanges undone in reverse order.
+ * Used by the condition estimator, which needs products with A^-T.  Same
+ * arguments and return values as orc_getrs. */
+int orc_getrs_trans(int n, const double *LU, int lda, const int *ipiv, double *B, int ldb,
+                    int nrhs) {
+  if (n < 0) return -1;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (ldb < (nrhs > 1 ? nrhs : 1)) return -6;
+  if (nrhs < 0) return -7;
+  for (int i = 0; i < n; ++i)
+    if (LU[(size_t)i * lda + i] == 0.0) return 1;
+  for (int c = 0; c < nrhs; ++c) {
+    /* U^T z = b: z_i = (b_i - sum_{j<i} u_ji z_j) / u_ii */
+    for (int i = 0; i < n; ++i) {
+      double s = B[(size_t)i * ldb + c];
+      for (int j = 0; j < i; ++j) {
+        const double prod = LU[(size_t)j * lda + i] * B[(size_t)j * ldb + c];
+        s = s - prod;
+      }
+      B[(size_t)i * ldb + c] = s / LU[(size_t)i * lda + i];
+    }
+    /* L^T w = z: w_i = z_i - sum_{j>i} l_ji w_j */
+    for (int i = n - 1; i >= 0; --i) {
+      double s = B[(size_t)i * ldb + c];
+      for (int j = i + 1; j < n; ++j) {
+        const double prod = LU[(size_t)j * lda + i] * B[(size_t)j * ldb + c];
+        s = s - prod;
+      }
+      B[(size_t)i * ldb + c] = s;
+    }
+  }
+  if (ipiv) {
+    for (int k = n - 1; k >= 0; --k) {
+      int p = ipiv[k];
+      if (p != k) {
+        for (int c = 0; c < nrhs; ++c) {
+          double t = B[(size_t)k * ldb + c];
+          B[(size_t)k * ldb + c] = B[(size_t)p * ldb + c];
+          B[(size_t)p * ldb + c] = t;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
 /* Scaled residual per right-hand side, binary64 with left-to-right sums.
  * out[5*c + 0..4] = { s, ||r||_inf, ||A||_inf, ||x_c||_inf, ||b_c||_inf } with
  * r = A x - b.  A NaN anywhere propagates into s (and s < 16 is then false). */

@@ -56,3 +56,29 @@ def test_rhs_layout():
     b = inputs.rhs(3, 10, 4)
     assert b.shape == (10, 4)
     assert b[2, 3] == scalar_value(3, 1, 2 * 4 + 3)
+
+
+def test_splitmix64_published_test_vector():
+    # SplitMix64 (Steele, Lea & Flood 2014) started from state 1234567: the
+    # first five outputs of the published reference generator.  word(idx) is
+    # mix64(state + (idx + 1) * golden gamma), so this pins the gamma, both
+    # multipliers and all three shifts.
+    known = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+             4593380528125082431, 16408922859458223821]
+    m = (1 << 64) - 1
+    got = [inputs.mix64_int((1234567 + (i + 1) * inputs.GOLDEN) & m) for i in range(5)]
+    assert got == known
+
+
+def test_frozen_known_answers():
+    # Frozen after the first run (seed 2202, the benchmark seed): the stream
+    # key, the counter layout and the value map must never change, or every
+    # stored expected value goes stale.
+    w0 = [int(v) for v in inputs.words(2202, 0, np.arange(4, dtype=np.uint64))]
+    assert w0 == [11679603653836149609, 2546826671173654124, 8944916027041204696,
+                  8505917649281692741]
+    w1 = [int(v) for v in inputs.words(2202, 1, np.arange(2, dtype=np.uint64))]
+    assert w1 == [3395646559196411040, 4722259662302294198]
+    a = inputs.matrix(2202, 4)
+    assert a[0, 0] == (11679603653836149609 >> 11) * 2.0 ** -53 - 0.5
+    assert a[0, 3] == (8505917649281692741 >> 11) * 2.0 ** -53 - 0.5

@@ -298,3 +298,81 @@ def test_row_residuals_match_full():
     r, _ = oracle.row_residuals(a, x, b)
     full = oracle.residual(a, x, b)
     assert np.allclose(np.max(np.abs(r), axis=0), full[:, 1], rtol=0, atol=0)
+
+
+# ------------------------------------------- scaling divides (reading: divide)
+def test_multipliers_are_correctly_rounded_quotients():
+    # The first column's multipliers are a single rounding of a_i0 / a_00.  A
+    # correctly rounded division gives float(Fraction(a_i0) / Fraction(a_00))
+    # exactly; multiplying by a rounded reciprocal does not (3 * (1/5) is
+    # 0.6000000000000001, while 3/5 rounds to 0.6).
+    a = np.array([[5.0, 1.0], [3.0, 2.0]])
+    lu, piv, info = oracle.getrf(a)
+    assert list(piv) == [0, 1] and info == 0
+    assert lu[1, 0] == float(Fraction(3, 5))
+    assert lu[1, 0] != 3.0 * (1.0 / 5.0)
+    # a whole column: pivot 10 (largest), many quotients where the two differ
+    col = np.array([10.0] + [float(v) for v in range(1, 10)] + [-3.0, 7.0, -9.0, 9.5])
+    a = col.reshape(-1, 1).copy()  # one column: one elimination step
+    for getrf in (lambda x: oracle.getrf(x)[0], lambda x: oracle.getrf_nopiv(x)[0]):
+        lu = getrf(a)
+        exact = [float(Fraction(v) / Fraction(10.0)) for v in col[1:]]
+        assert list(lu[1:, 0]) == exact
+    recip = col[1:] * (1.0 / 10.0)
+    assert np.count_nonzero(recip != np.array(exact)) >= 3
+
+
+# ------------------------------------------------- transposed solve, estimate
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_transposed_solve_matches_exact(n):
+    rng = np.random.default_rng(300 + n)
+    a = dyadic_matrix(rng, n, n)
+    lu_x, piv_x, info_x = brute.getrf_exact(a)
+    if info_x != 0:
+        a = a + n * np.eye(n)
+    b = dyadic_matrix(rng, n, 1)[:, 0]
+    x_exact = np.array([float(v) for v in brute.solve_exact(a.T.copy(), b)])
+    lu, piv, info = oracle.getrf(a)
+    x = oracle.getrs(lu, piv, b, trans=True)
+    assert rel(x, x_exact) <= 1e-12
+
+
+def test_transposed_solve_generic():
+    rng = np.random.default_rng(5)
+    a = rng.uniform(-0.5, 0.5, (200, 200))
+    b = rng.uniform(-0.5, 0.5, (200, 3))
+    lu, piv, _ = oracle.getrf(a)
+    x = oracle.getrs(lu, piv, b, trans=True)
+    assert rel(a.T @ x, b) <= 1e-11
+    assert rel(x, np.linalg.solve(a.T, b)) <= 1e-10
+
+
+def test_condition_estimate_exact_cases():
+    from oracle import cond
+    # diagonal: ||A^-1||_inf = max 1/|d_i|, found exactly
+    d = np.array([4.0, -0.5, 2.0, 8.0, -0.25])
+    lu, piv, _ = oracle.getrf(np.diag(d))
+    assert cond.inv_norm_inf_estimate(lu, piv) == 4.0
+    # second difference matrix: closed-form inverse min(i,j)(n+1-max(i,j))/(n+1)
+    for n in (7, 40, 101):
+        a = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+        i = np.arange(1, n + 1)
+        inv = np.minimum.outer(i, i) * (n + 1 - np.maximum.outer(i, i)) / (n + 1)
+        exact = np.abs(inv).sum(axis=1).max()
+        lu, piv, _ = oracle.getrf(a)
+        assert abs(cond.inv_norm_inf_estimate(lu, piv) - exact) <= 1e-12 * exact
+
+
+def test_condition_estimate_is_a_lower_bound():
+    from oracle import cond
+    import inputs
+    hits = 0
+    for seed in range(1, 9):
+        a = inputs.matrix(seed, 120)
+        lu, piv, _ = oracle.getrf(a)
+        est = cond.inv_norm_inf_estimate(lu, piv)
+        exact = np.abs(np.linalg.inv(a)).sum(axis=1).max()
+        assert est <= exact * (1 + 1e-10)
+        assert est >= exact / 3
+        hits += abs(est - exact) <= 1e-10 * exact
+    assert hits >= 6

@@ -1,14 +1,19 @@
 """Benchmark of the dense LU solve path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 32768] [--nb 256]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 65536] [--nb 512]
 
 One step is one pass of the whole path over one synthetic system: blocked LU
 factorization with partial pivoting (panel, row exchanges, triangular solve,
 inner-block update, look-ahead), forward/back substitution and the benchmark's
-scaled-residual check.  The K systems are generated on the device and copied
-into K separate buffers before the timed region, so every timed step starts
-from inputs already resident in HBM.  `value` is K * (2/3 n^3 + 2 n^2) flops
-over the wall time of the K steps (LINPACK's operation count).
+scaled-residual check.  The default workload is the largest single-GPU
+configuration: n = 65536, nb = 512, A and b uniform[-0.5, 0.5) from seed 2202,
+unshifted.  The system is generated once on the device; before every step
+(warm-up and timed) the working matrix and right-hand side are restored from
+that copy outside the timed interval, so every timed step starts from inputs
+already resident in HBM.  Each step is bracketed by device synchronizations
+and timed on the host clock; `value` is K * (2/3 n^3 + 2 n^2) flops over the
+sum of the K step times (LINPACK's operation count), and the best, median and
+mean step times are reported beside it.
 
 The line also carries the roofline of the dominant kernel (the FP64 trailing
 update, bound by the FP64 matrix-core peak), measured with HIP events around
@@ -16,12 +21,18 @@ each of its launches during the timed steps, its HBM traffic per launch from
 the committed rocprofv3 counter summary (null if the kernel source changed
 since), and the CPU oracle timed on a bounded sample on this host.
 
-Two more objects ride on the same line: `mixed_ir` (n = 65536 solved through
-the bfloat16 factorization plus binary64 refinement on A + n I, with the
-binary64 path timed on that same system for the speedup) and `serving` (an
-open-loop Poisson stream through the continuous-batching server: p50/p99
-latency overall and per request class, and aggregate TFLOP/s).  One process, one GPU; prints
-one JSON line on stdout, progress on stderr.
+More objects ride on the same line:
+  * `x_parity`: the binary64 path at n = 32768 against the oracle's stored
+    solution of that system (forward error next to the host-LAPACK noise
+    floor, pivot agreement), when the stored solution is present;
+  * `mixed_ir` (n = 65536 solved through the bfloat16 factorization plus
+    binary64 refinement on A + n I, with the binary64 path timed on that same
+    system the same number of times for the speedup);
+  * `mixed_ir_unshifted` (the same route on the unshifted headline system:
+    refinement history, fallback, and the time with and without it);
+  * `serving` (an open-loop Poisson stream through the continuous-batching
+    server: p50/p99 latency overall and per request class, aggregate TFLOP/s).
+One process, one GPU; prints one JSON line on stdout, progress on stderr.
 """
 from __future__ import annotations
 
@@ -47,6 +58,17 @@ def flops(n: int, nrhs: int = 1) -> float:
     return 2.0 / 3.0 * n ** 3 + 2.0 * n ** 2 * nrhs
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n: int, seed: int) -> dict:
     """The oracle (unblocked GEPP + solves) on this host, on one n x n system."""
     import oracle
@@ -60,8 +82,73 @@ def cpu_baseline(n: int, seed: int) -> dict:
     dt = time.perf_counter() - t0
     return {"value": flops(n) / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
             "kind": "oracle", "seconds": dt,
+            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
             "sample": f"one FP64 system n={n} (LU with partial pivoting + solve), "
                       f"uniform[-0.5,0.5) seed {seed}; same operation count formula"}
+
+
+def stats_ms(times_s) -> dict:
+    import statistics
+    ms = [1e3 * t for t in times_s]
+    return {"best_ms": min(ms), "median_ms": statistics.median(ms),
+            "mean_ms": sum(ms) / len(ms), "reps": len(ms)}
+
+
+def load_golden(n: int, seed: int):
+    """The oracle's stored solution of the (n, seed) system, or None."""
+    import numpy as np
+    base = os.path.join(ROOT, "tests", "golden", f"fullsize_n{n}_seed{seed}")
+    if not os.path.exists(base + ".npz"):
+        return None
+    with np.load(base + ".npz", allow_pickle=False) as z:
+        g = {"x": z["x"], "ipiv": z["ipiv"]}
+    with open(base + ".json") as f:
+        g.update(json.load(f))
+    return g
+
+
+def forward_error(x, x_ref) -> float:
+    """max |x - x_ref| / max |x_ref| (device tensors or host arrays)."""
+    import numpy as np
+
+    def host(v):
+        if hasattr(v, "detach"):
+            v = v.detach().cpu().numpy()
+        return np.asarray(v, dtype=np.float64).reshape(-1)
+    x, r = host(x), host(x_ref)
+    return float(np.max(np.abs(x - r)) / np.max(np.abs(r)))
+
+
+def bench_x_parity(lp, inputs, torch, dev, n, nb, seed):
+    """The binary64 path on the (n, seed) system against the oracle's stored
+    solution: forward error, the host-LAPACK noise floor and kappa estimate
+    stored with it, pivot agreement, and both scaled residuals."""
+    import numpy as np
+    g = load_golden(n, seed)
+    if g is None:
+        return None
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    inputs.fill_matrix_(A, seed)
+    B = torch.empty((n, 1), dtype=torch.float64, device=dev)
+    inputs.fill_rhs_(B, seed)
+    A0 = A.clone()
+    X = B.clone()
+    ipiv, info = lp.lu_factor(A, nb, "fp64")
+    lp.lu_solve(A, ipiv, info, X)
+    out = lp.residual_check(A0, X, B).cpu().numpy()
+    piv = ipiv.cpu().numpy()[:n]
+    rel = forward_error(X, g["x"])
+    del A, A0
+    torch.cuda.empty_cache()
+    return {"n": n, "nb": nb, "seed": seed,
+            "forward_error_vs_oracle": rel,
+            "noise_floor_lapack_vs_oracle": g["lapack_rel_x_diff"],
+            "kappa_inf_estimate": g["kappa_inf_estimate"],
+            "pivot_agreement": float(np.mean(piv == g["ipiv"])),
+            "scaled_residual": float(out[0, 0]),
+            "oracle_scaled_residual": g["scaled_residual"],
+            "oracle_factor_s": g["oracle_factor_s"], "oracle_threads": g["oracle_threads"],
+            "oracle_host_cpu": g["host_cpu"]}
 
 
 PEAK_LOWP_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # dense MFMA peaks
@@ -87,10 +174,14 @@ def traffic_from_profile(kernel_src: str, n: int, nb: int):
     return float(m_b.group(1))
 
 
-def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, K, W, nrhs):
-    """K solves of one system through the low-precision factorization plus
-    binary64 refinement (and the binary64 fallback when refinement fails),
-    with the binary64 blocked path timed once on the same system beside it."""
+def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_leg=True,
+                x_ref=None, x_ref_label=None):
+    """R timed solves (after one untimed) of one system through the
+    low-precision factorization plus binary64 refinement (and the binary64
+    fallback when refinement fails).  With fp64_leg the binary64 blocked path
+    is timed on that same system the same way, for the speedup.  The forward
+    error is taken against x_ref (the oracle's or the binary64 path's x) and
+    the backward error is the scaled residual."""
     A = torch.empty((n, n), dtype=torch.float64, device=dev)
     inputs.fill_matrix_(A, seed, shift=shift)
     B = torch.empty((n, nrhs), dtype=torch.float64, device=dev)
@@ -98,54 +189,70 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, K, W, nrhs):
     X = torch.empty_like(B)
     nbytes = lp.lib.lu_solve_ir_workspace_bytes(n, nb, lp.PREC[prec], nrhs)
     work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    for w in range(W):
-        lp.solve_ir(A, B, nb, prec, X=X, work=work)
+    lp.solve_ir(A, B, nb, prec, X=X, work=work)
     torch.cuda.synchronize()
-    reps = []
-    t0 = time.perf_counter()
-    for _ in range(K):
+    reps, times = [], []
+    for _ in range(R):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         _, rep = lp.solve_ir(A, B, nb, prec, X=X, work=work)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
         reps.append(rep.as_dict())
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / K
     del work
-    # binary64 path on the same system, one solve (factor + solve + check)
-    A64 = A.clone()
-    X64 = B.clone()
-    w64 = lp.workspace(n, nb, "fp64", dev)
-    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
-    info = torch.empty(1, dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lp.lu_factor(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
-    lp.lu_solve(A64, ipiv, info, X64)
-    out = lp.residual_check(A, X64, B)
-    torch.cuda.synchronize()
-    dt64 = time.perf_counter() - t0
-    s64 = float(out[:, 0].max().item())
-    del A64, X64, w64
+    st = stats_ms(times)
+    dt = st["median_ms"] * 1e-3
     last = reps[-1]
     eff = flops(n, nrhs) / dt / 1e12
-    return {
+    res = {
         "workload": f"{prec.upper()} LU (binary32 panels, {prec} update operands, binary32 "
                     f"accumulation) + binary64 refinement to scaled residual < 16, n={n}, "
                     f"nb={nb}, nrhs={nrhs}, A uniform[-0.5,0.5) "
                     + (f"+ {shift:g} I" if shift else "unshifted") + f", seed {seed}",
         "prec": prec, "n": n, "nb": nb, "shift": shift,
-        "ms_per_solve": 1e3 * dt,
+        "ms_per_solve": st["median_ms"], "times": st,
         "effective_tflops": eff,
-        "frac_fp64_peak": eff / PEAK_FP64_TFLOPS,
+        "effective_over_fp64_peak": eff / PEAK_FP64_TFLOPS,
         "frac_lowp_peak": eff / PEAK_LOWP_TFLOPS[prec],
-        "fp64_ms_same_system": 1e3 * dt64,
-        "fp64_scaled_residual_same_system": s64,
-        "speedup_vs_fp64": dt64 / dt,
         "iterations": last["iterations"], "converged": last["converged"],
         "fell_back": last["fell_back"], "scaled_residual": last["scaled_residual"],
+        "backward_error_scaled_residual": last["scaled_residual"],
         "history": last["history"],
         "phase_ms": {k: last[k] for k in ("t_convert_ms", "t_factor_ms", "t_solve0_ms",
                                           "t_refine_ms", "t_fallback_ms", "t_total_ms")},
+        "ms_without_fallback": last["t_total_ms"] - last["t_fallback_ms"],
         "residual_pass": bool(last["scaled_residual"] < 16.0),
     }
+    if fp64_leg:
+        A64 = torch.empty_like(A)
+        X64 = torch.empty_like(B)
+        w64 = lp.workspace(n, nb, "fp64", dev)
+        ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        t64 = []
+        out = None
+        for r in range(R + 1):
+            A64.copy_(A)
+            X64.copy_(B)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lp.lu_factor(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
+            lp.lu_solve(A64, ipiv, info, X64)
+            out = lp.residual_check(A, X64, B)
+            torch.cuda.synchronize()
+            if r > 0:  # the first solve is the untimed warm-up
+                t64.append(time.perf_counter() - t0)
+        st64 = stats_ms(t64)
+        res["fp64_same_system"] = dict(st64, scaled_residual=float(out[:, 0].max().item()))
+        res["fp64_ms_same_system"] = st64["median_ms"]
+        res["speedup_vs_fp64"] = st64["median_ms"] / st["median_ms"]
+        res["forward_error_vs_fp64_path"] = forward_error(X, X64)
+        del A64, w64
+    if x_ref is not None:
+        res["forward_error_vs_" + x_ref_label] = forward_error(X, x_ref)
+    del A
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small_n_max=512,
@@ -241,10 +348,10 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=32768)
-    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2202)
     ap.add_argument("--no-lookahead", action="store_true")
@@ -257,9 +364,15 @@ def main() -> int:
     ap.add_argument("--mixed-n", type=int, default=65536,
                     help="order of the mixed-precision system (0: --n)")
     ap.add_argument("--mixed-nb", type=int, default=512, help="0: --nb")
-    ap.add_argument("--mixed-unshifted", action="store_true",
-                    help="no n*I diagonal shift (refinement may fail and fall back)")
+    ap.add_argument("--mixed-reps", type=int, default=3,
+                    help="timed solves per mixed-precision leg (after one untimed)")
+    ap.add_argument("--no-mixed-unshifted", action="store_true",
+                    help="skip the unshifted mixed-precision record")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--parity-n", type=int, default=32768,
+                    help="order of the system compared with the oracle's stored solution")
+    ap.add_argument("--parity-nb", type=int, default=256)
+    ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=100.0,
                     help="offered requests per second (about 3/4 of the measured saturation)")
@@ -288,10 +401,6 @@ def main() -> int:
     dev = torch.device("cuda:0")
     n, nb, K, W = args.n, args.nb, args.steps, args.warmup
     free, total = torch.cuda.mem_get_info()
-    need = (K + 2) * 8 * n * n
-    if need > 0.9 * free:
-        K = max(1, int(0.9 * free // (8 * n * n)) - 2)
-        log(f"[bench] memory allows {K} timed copies")
     log(f"[bench] n={n} nb={nb} steps={K} warmup={W} free={free / 2**30:.1f} GiB")
 
     A0 = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -314,37 +423,39 @@ def main() -> int:
                  "write_bytes": 4 * rows * n}
         del dst
 
-    # warm-up on a scratch copy
-    scratch = torch.empty_like(A0)
+    A = torch.empty_like(A0)
+    X = torch.empty_like(B0)
     for w in range(W):
-        scratch.copy_(A0)
-        X = B0.clone()
-        lp.lu_factor(scratch, nb, "fp64", work=work, ipiv=ipiv, info=info, lookahead=look,
+        A.copy_(A0)
+        X.copy_(B0)
+        lp.lu_factor(A, nb, "fp64", work=work, ipiv=ipiv, info=info, lookahead=look,
                      panel_cus=args.panel_cus, panel_rows=args.panel_rows)
-        lp.lu_solve(scratch, ipiv, info, X)
+        lp.lu_solve(A, ipiv, info, X)
         lp.residual_check(A0, X, B0)
         torch.cuda.synchronize()
         log(f"[bench] warm-up {w + 1}/{W} done")
-    del scratch
 
-    As = [A0.clone() for _ in range(K)]
-    Xs = [B0.clone() for _ in range(K)]
     outs = [torch.empty((args.nrhs, 5), dtype=torch.float64, device=dev) for _ in range(K)]
     infos = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(K)]
     profs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    step_s = []
     for i in range(K):
-        _, _, prof = lp.lu_factor(As[i], nb, "fp64", work=work, ipiv=ipiv, info=infos[i],
+        A.copy_(A0)  # restore the input: outside the timed interval
+        X.copy_(B0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, prof = lp.lu_factor(A, nb, "fp64", work=work, ipiv=ipiv, info=infos[i],
                                   lookahead=look, profile=True, panel_cus=args.panel_cus,
                                   panel_rows=args.panel_rows)
-        lp.lu_solve(As[i], ipiv, infos[i], Xs[i])
-        lp.residual_check(A0, Xs[i], B0, out=outs[i])
+        lp.lu_solve(A, ipiv, infos[i], X)
+        lp.residual_check(A0, X, B0, out=outs[i])
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t0)
         profs.append(prof)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    log(f"[bench] timed {K} steps in {elapsed:.3f} s")
+        log(f"[bench] step {i + 1}/{K}: {1e3 * step_s[-1]:.1f} ms")
+    elapsed = sum(step_s)
+    log(f"[bench] timed {K} steps: {elapsed:.3f} s")
+    x_head = X.clone()
 
     res = torch.stack(outs).cpu().numpy()
     s_max = float(res[:, :, 0].max())
@@ -375,6 +486,7 @@ def main() -> int:
         "steps": K,
         "warmup": W,
         "ms_per_step": 1e3 * elapsed / K,
+        "step_times": stats_ms(step_s),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -382,11 +494,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"FP64 blocked LU with partial pivoting + solve + residual "
                                f"check, n={n}, nb={nb}, nrhs={args.nrhs}, A and b "
-                               f"uniform[-0.5,0.5) seed {args.seed}",
+                               f"uniform[-0.5,0.5) seed {args.seed}, unshifted",
                    "n": n, "nb": nb, "nrhs": args.nrhs, "lookahead": look,
                    "panel_cus": args.panel_cus, "panel_rows": args.panel_rows},
         "frac_fp64_peak": value / PEAK_FP64_TFLOPS,
         "scaled_residual_max": s_max,
+        "backward_error_scaled_residual": s_max,
         "residual_pass": bool(info_ok and s_max < 16.0),
         "roofline": {"kernel": "dgemm_trailing_update", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -396,17 +509,39 @@ def main() -> int:
                      max(gemm_launches, 1)},
         "phases_ms_per_step": phases,
     }
-    del As, Xs
+    del A, A0, X
     torch.cuda.empty_cache()
+    g_head = load_golden(n, args.seed)
+    if g_head is not None:
+        line["forward_error_vs_oracle"] = forward_error(x_head, g_head["x"])
+    if not args.no_parity and args.parity_n != n:
+        log(f"[bench] x-parity n={args.parity_n} against the stored oracle solution ...")
+        line["x_parity"] = bench_x_parity(lp, inputs, torch, dev, args.parity_n,
+                                          args.parity_nb, args.seed)
+    R = max(1, args.mixed_reps)
     if not args.no_mixed:
         mn = args.mixed_n or n
         mnb = args.mixed_nb or nb
-        shift = 0.0 if args.mixed_unshifted else float(mn)
-        log(f"[bench] mixed {args.mixed_prec} n={mn} nb={mnb} shift={shift:g} ...")
-        line["mixed_ir"] = bench_mixed(lp, inputs, torch, dev, mn, mnb, args.mixed_prec, shift,
-                                       args.seed, K, W, args.nrhs)
+        log(f"[bench] mixed {args.mixed_prec} n={mn} nb={mnb} shift={mn} ...")
+        line["mixed_ir"] = bench_mixed(lp, inputs, torch, dev, mn, mnb, args.mixed_prec,
+                                       float(mn), args.seed, R, args.nrhs)
         log(f"[bench] mixed done: {line['mixed_ir']['ms_per_solve']:.1f} ms/solve, "
             f"speedup {line['mixed_ir']['speedup_vs_fp64']:.2f}x")
+        if not args.no_mixed_unshifted:
+            same = mn == n and mnb == nb
+            log(f"[bench] mixed {args.mixed_prec} n={mn} unshifted ...")
+            line["mixed_ir_unshifted"] = bench_mixed(
+                lp, inputs, torch, dev, mn, mnb, args.mixed_prec, 0.0, args.seed,
+                max(1, R - 1), args.nrhs, fp64_leg=False,
+                x_ref=(g_head["x"] if g_head is not None else x_head) if same else None,
+                x_ref_label="oracle" if g_head is not None else "fp64_path")
+            if same:
+                mu = line["mixed_ir_unshifted"]
+                mu["fp64_ms_same_system"] = line["step_times"]["median_ms"]
+                mu["speedup_vs_fp64"] = mu["fp64_ms_same_system"] / mu["ms_per_solve"]
+            log(f"[bench] mixed unshifted done: "
+                f"{line['mixed_ir_unshifted']['ms_per_solve']:.1f} ms/solve, fell back "
+                f"{line['mixed_ir_unshifted']['fell_back']}")
         torch.cuda.empty_cache()
     if not args.no_serve:
         log(f"[bench] serving {args.serve_requests} requests at {args.serve_rate:g}/s ...")

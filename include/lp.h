@@ -103,6 +103,8 @@ typedef struct {
                      of 8; the CU mask interleaves over the XCDs) */
   int panel_rows; /* panels of at most this many rows use the reserved units;
                      0 (default): min(1024 * panel_cus, 3 n / 4) */
+  int no_pivoting;  /* 0 (default): partial pivoting; 1: no row exchanges, as
+                       lu_factor_nopiv (panel_cus / panel_rows are then unused) */
 } lp_factor_opts;
 
 typedef struct {
@@ -124,6 +126,26 @@ typedef struct {
 int lu_factor_ex(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
                  void *work, size_t work_bytes, const lp_factor_opts *opts,
                  lp_factor_profile *prof, void *stream);
+
+/* LU factorization WITHOUT pivoting, A = L U: the paper's own elimination
+ * (section "High Performance Linpack": the inputs are made diagonally
+ * dominant, the HPL-AI rule, so no pivoting is needed; "Base
+ * Implementation", figure fig:lu_iteration).  Per block column of width nb:
+ * the nb x nb diagonal block is decomposed in one workgroup with no pivot
+ * search (the paper's LU kernel), the blocks below it are solved against its
+ * upper triangle, L21 = A21 U11^-1, on the matrix cores (the "left" blocks),
+ * the blocks right of it against its unit lower triangle (the "top" blocks),
+ * and the inner blocks are updated with one multiplication; the next block
+ * column's diagonal and left blocks are factored beside the rest of the
+ * multiplication.  No row exchanges run at all.
+ * Arguments, layout, workspace (lu_workspace_bytes) and errors as lu_factor;
+ * ipiv (device int32[n]) receives the identity so that lu_solve applies
+ * unchanged.  *info = k + 1 for the first exact zero pivot u_kk (the factors
+ * past it are then not meaningful).  Intended for matrices that need no
+ * pivoting (e.g. diagonally dominant); on others the elimination may be
+ * unstable, and nothing checks for that. */
+int lu_factor_nopiv(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
+                    void *work, size_t work_bytes, void *stream);
 
 /* ----------------------------------------------------------------- solve */
 
@@ -267,9 +289,18 @@ size_t lp_request_footprint(const lp_server_cfg *cfg, const lp_request *req);
  * ipiv[0..w-1] receive panel-relative pivot rows; *info as lu_factor
  * (panel-relative column).  The interchanges are applied to the w panel
  * columns only.  work: lu_workspace_bytes(m, w, prec) bytes.  prec selects
- * double (LP_FP64) or float (others). */
+ * double (LP_FP64) or float (others).
+ *   max_wgs  0: the panel is spread over the whole device (one workgroup per
+ *            at most 256 rows), the shape lu_factor uses for its first panel
+ *            and without look-ahead; k > 0: at most k workgroups of up to
+ *            1024 rows each, the shape lu_factor uses for panels factored
+ *            beside the trailing update (max(48, ceil(m / 1024)) binary64,
+ *            max(128, ceil(m / 1024)) binary32).  LP_ENOTSUP when m > 1024 k;
+ *            -10 when k < 0.
+ * Results do not depend on max_wgs (the pivot choice and the arithmetic of
+ * each element are the same); only the launch shape does. */
 int lp_panel_factor(int m, int w, int prec, void *A, int lda, int32_t *ipiv,
-                    int32_t *info, void *work, size_t work_bytes, void *stream);
+                    int32_t *info, void *work, size_t work_bytes, int max_wgs, void *stream);
 
 /* Row interchanges: for j = k1 .. k2-1 in order, swap rows j and ipiv[j]
  * (absolute row indices, ipiv[j] >= j) over columns [c0, c1) of A (double if
@@ -286,6 +317,16 @@ int lp_laswp(int prec, void *A, int lda, int c0, int c1, int k1, int k2,
 size_t lp_trsm_workspace_bytes(int m);
 int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void *B, int ldb,
                        void *work, size_t work_bytes, void *stream);
+
+/* Right-side triangular solve with an upper, non-unit triangle U (w x w, ld
+ * ldu; entries below its diagonal are not read): B := B U^-1 for B m x w (ld
+ * ldb), in place.  Rows are independent.  The "left blocks" update of the
+ * paper's no-pivot scheme (L21 U11 = A21).  w <= 1024.  work: device scratch
+ * of lp_trsm_right_workspace_bytes(w) bytes (transposed inverses of the
+ * 16 x 16 diagonal blocks of U).  A zero on U's diagonal gives Inf/NaN. */
+size_t lp_trsm_right_workspace_bytes(int w);
+int lp_trsm_right_upper(int prec, int m, int w, const void *U, int ldu, void *B, int ldb,
+                        void *work, size_t work_bytes, void *stream);
 
 /* Inner-block update C := C - A B with A M x K (lda), B K x N (ldb), C M x N
  * (ldc); prec LP_FP64: all double on FP64 MFMA; LP_FP32: float operands on

@@ -47,7 +47,7 @@ class IRReport(ctypes.Structure):
 
 class FactorOpts(ctypes.Structure):
     _fields_ = [("lookahead", ctypes.c_int), ("panel_cus", ctypes.c_int),
-                ("panel_rows", ctypes.c_int)]
+                ("panel_rows", ctypes.c_int), ("no_pivoting", ctypes.c_int)]
 
 
 class FactorProfile(ctypes.Structure):
@@ -97,6 +97,7 @@ SIGNATURES = {
     "lu_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lu_factor_ex": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, ctypes.POINTER(FactorOpts),
                           ctypes.POINTER(FactorProfile), _VP]),
+    "lu_factor_nopiv": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lu_solve": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP]),
     "residual_check": (_I, [_I, _VP, _I, _VP, _I, _VP, _I, _I, _VP, _VP]),
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
@@ -111,11 +112,13 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_size_t)]),
     "lp_request_footprint": (_SZ, [ctypes.POINTER(ServerCfg), ctypes.POINTER(Request)]),
     "lp_ir_decide": (_I, [ctypes.POINTER(ctypes.c_double), _I, _I, _I]),
-    "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "lp_panel_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _I, _VP]),
     "lp_laswp_workspace_bytes": (_SZ, [_I]),
     "lp_laswp": (_I, [_I, _VP, _I, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "lp_trsm_workspace_bytes": (_SZ, [_I]),
     "lp_trsm_lower_unit": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
+    "lp_trsm_right_workspace_bytes": (_SZ, [_I]),
+    "lp_trsm_right_upper": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
     "lp_gemm_update": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
     "lp_gemm_packed_workspace_bytes": (_SZ, [_I, _I, _I]),
     "lp_gemm_update_packed": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
@@ -165,6 +168,14 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def _keep(t: torch.Tensor, stream) -> None:
+    """A tensor allocated here and dropped on return is freed to torch's caching
+    allocator on the current stream; when the work was queued on another stream,
+    mark it used there so the block is not handed out before that work ends."""
+    if stream is not None and t is not None:
+        t.record_stream(stream)
+
+
 def _mat(t: torch.Tensor, dtype=None, name="matrix") -> int:
     if not t.is_cuda:
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
@@ -192,11 +203,12 @@ def workspace(n: int, nb: int, prec="fp64", device="cuda") -> torch.Tensor:
 
 def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
               stream=None, lookahead: bool = True, profile: bool = False,
-              panel_cus: int = 0, panel_rows: int = 0):
+              panel_cus: int = 0, panel_rows: int = 0, pivot: bool = True):
     """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device, plus a
     per-phase profile dict when profile=True (the call then synchronizes).
     panel_cus / panel_rows: compute units reserved for short panels (see
-    lp_factor_opts in include/lp.h; 0 / 0: never)."""
+    lp_factor_opts in include/lp.h; 0 / 0: never).  pivot=False: the no-pivot
+    elimination of lu_factor_nopiv (ipiv is then the identity)."""
     p = _prec(prec)
     lda = _mat(A, storage_dtype(p), "A")
     n = A.shape[0]
@@ -208,13 +220,14 @@ def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=
         ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
-    opts = FactorOpts(1 if lookahead else 0, panel_cus, panel_rows)
+    opts = FactorOpts(1 if lookahead else 0, panel_cus, panel_rows, 0 if pivot else 1)
     prof = FactorProfile() if profile else None
     _check("lu_factor", _lib().lu_factor_ex(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
                                          info.data_ptr(), work.data_ptr(), work.numel(),
                                          ctypes.byref(opts),
                                          ctypes.byref(prof) if prof is not None else None,
                                          _stream(stream)))
+    _keep(work, stream)
     if profile:
         return ipiv, info, prof.as_dict()
     return ipiv, info
@@ -273,6 +286,7 @@ def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: i
     _check("lu_solve_ir", _lib().lu_solve_ir(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
                                           X.data_ptr(), ldx, nrhs, max_iter, work.data_ptr(),
                                           work.numel(), ctypes.byref(rep), _stream(stream)))
+    _keep(work, stream)
     return X, rep
 
 
@@ -369,7 +383,10 @@ class Server:
 
 
 # ------------------------------------------------------------ building blocks
-def panel_factor(P: torch.Tensor, prec="fp64", work=None, stream=None):
+def panel_factor(P: torch.Tensor, prec="fp64", work=None, stream=None, max_wgs: int = 0):
+    """Partial-pivoting LU of the column panel P (m x w) in place. Returns (ipiv, info).
+    max_wgs > 0 launches at most that many workgroups of up to 1024 rows (the
+    shape of panels factored beside the trailing update)."""
     p = _prec(prec)
     ld = _mat(P, storage_dtype(p), "panel")
     m, w = P.shape
@@ -379,7 +396,8 @@ def panel_factor(P: torch.Tensor, prec="fp64", work=None, stream=None):
     info = torch.empty(1, dtype=torch.int32, device=P.device)
     _check("lp_panel_factor", _lib().lp_panel_factor(m, w, p, P.data_ptr(), ld, ipiv.data_ptr(),
                                                   info.data_ptr(), work.data_ptr(),
-                                                  work.numel(), _stream(stream)))
+                                                  work.numel(), max_wgs, _stream(stream)))
+    _keep(work, stream)
     return ipiv, info
 
 
@@ -391,6 +409,7 @@ def laswp(A: torch.Tensor, c0: int, c1: int, k1: int, k2: int, ipiv: torch.Tenso
     work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=A.device)
     _check("lp_laswp", _lib().lp_laswp(p, A.data_ptr(), lda, c0, c1, k1, k2, ipiv.data_ptr(),
                                     work.data_ptr(), work.numel(), _stream(stream)))
+    _keep(work, stream)
 
 
 def trsm_lower_unit(L: torch.Tensor, B: torch.Tensor, stream=None) -> None:
@@ -403,6 +422,44 @@ def trsm_lower_unit(L: torch.Tensor, B: torch.Tensor, stream=None) -> None:
     _check("lp_trsm_lower_unit", _lib().lp_trsm_lower_unit(p, m, B.shape[1], L.data_ptr(), ldl,
                                                            B.data_ptr(), ldb, work.data_ptr(),
                                                            work.numel(), _stream(stream)))
+    _keep(work, stream)
+
+
+def trsm_right_upper(U: torch.Tensor, B: torch.Tensor, stream=None) -> None:
+    """In place: B := B U^-1 with U upper triangular, non-unit (w x w)."""
+    p = FP64 if B.dtype == torch.float64 else FP32
+    ldu = _mat(U, B.dtype, "U")
+    ldb = _mat(B, B.dtype, "B")
+    m, w = B.shape
+    if U.shape[0] != w or U.shape[1] < w:
+        raise ValueError("U must be w x w")
+    nbytes = _lib().lp_trsm_right_workspace_bytes(w)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=B.device)
+    _check("lp_trsm_right_upper", _lib().lp_trsm_right_upper(p, m, w, U.data_ptr(), ldu,
+                                                             B.data_ptr(), ldb, work.data_ptr(),
+                                                             work.numel(), _stream(stream)))
+    _keep(work, stream)
+
+
+def lu_factor_nopiv(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
+                    stream=None):
+    """In place: A := L\\U without row exchanges (lu_factor_nopiv). Returns (ipiv, info)."""
+    p = _prec(prec)
+    lda = _mat(A, storage_dtype(p), "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if work is None:
+        work = workspace(n, nb, p, A.device)
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check("lu_factor_nopiv", _lib().lu_factor_nopiv(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
+                                                     info.data_ptr(), work.data_ptr(),
+                                                     work.numel(), _stream(stream)))
+    _keep(work, stream)
+    return ipiv, info
 
 
 def gemm_update(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=None,
@@ -443,6 +500,7 @@ def gemm_update_packed(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=B
            _lib().lp_gemm_update_packed(p, M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
                                         C.data_ptr(), ldc, work.data_ptr(), work.numel(),
                                         _stream(stream)))
+    _keep(work, stream)
 
 
 def convert(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

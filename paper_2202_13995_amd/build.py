@@ -26,8 +26,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
-SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "panel_fused.hip", "solve.hip", "driver.hip",
-           "ir.hip", "serve.hip"]
+SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "panel_fused.hip", "nopiv.hip", "solve.hip",
+           "driver.hip", "ir.hip", "serve.hip"]
 
 
 def _run(cmd):
@@ -44,16 +44,29 @@ def _compile(src: str, obj: str):
     return _run([HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj])
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source (always, so the build check is real)."""
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than src or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "lp.h"))
+    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every HIP source (always, so the build check is real), or with
+    incremental=True only those whose object is older than the sources."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     objs = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in srcs]
     jobs = int(os.environ.get("MAX_JOBS", "8"))
+    gen_obj = os.path.join(BUILD, "inputs_gen.o")
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, 16))) as ex:
-        futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in zip(srcs, objs)]
-        gen_obj = os.path.join(BUILD, "inputs_gen.o")
-        futs.append(ex.submit(_compile, GEN_SRC, gen_obj))
+        futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in zip(srcs, objs)
+                if not incremental or _stale(os.path.join(CSRC, s), o)]
+        if not incremental or _stale(GEN_SRC, gen_obj):
+            futs.append(ex.submit(_compile, GEN_SRC, gen_obj))
         for f in futs:
             msg = f.result()
             if verbose and msg.strip():
@@ -68,4 +81,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

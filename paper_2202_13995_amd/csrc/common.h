@@ -84,12 +84,21 @@ size_t panel_staging_bytes(int W);
 // max_wgs > 0: the launch runs on a stream restricted to that many compute
 // units, so it uses at most max_wgs workgroups (up to 1024 rows each) and
 // returns LP_ENOTSUP when the rows do not fit.
+// nopiv: no pivot search, the diagonal row is every column's pivot (ipiv[j] =
+// j); only for at most 1024 rows (one workgroup), else LP_ENOTSUP.
 size_t panel_keys_bytes();
 constexpr int kPanelRowsPerWg = 1024;
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s, int max_wgs = 0);
+                       void* keys_next, hipStream_t s, int max_wgs = 0, bool nopiv = false);
+
+// X U = B for X, U upper triangular (non-unit) w x w, B m x w (ld ldb), in
+// place: B := B U^-1 (the "left blocks" of the no-pivot LU).  work:
+// trsm_workspace_bytes(min(w, 128)) bytes.
+template <typename T>
+int launch_trsm_right_upper(int m, int w, const T* U, long long ldu, T* B, long long ldb,
+                            void* work, hipStream_t s);
 
 // Factorization / solve / residual (driver.hip, solve.hip), used by the IR driver.
 template <typename T>

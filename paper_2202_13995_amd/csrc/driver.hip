@@ -4,10 +4,9 @@
 // Implementation" (section "High Performance Linpack", figure fig:lu_iteration)
 // one block column of width nb at a time:
 //   1. factor the column panel (diagonal block plus the "left" blocks below it)
-//      with partial pivoting -- recursively: split the panel in two, factor the
-//      left half, exchange rows / solve / update the right half, factor the
-//      right half, exchange rows in the left half; the narrow leaves (<= 32
-//      columns) run as one kernel with a grid barrier per column;
+//      with partial pivoting in one persistent launch (panel_fused.hip): the
+//      workgroups split the panel's rows, exchange one candidate row per
+//      column, and factor leaves of 16 or 32 columns held in registers;
 //   2. apply the panel's row exchanges to every column outside the panel;
 //   3. solve the "top" blocks with the panel's unit lower triangle;
 //   4. update the "inner" blocks with one matrix multiplication.
@@ -61,7 +60,7 @@ constexpr int kPlanRing = 4;
 
 struct FactorLayout {
   size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, plan_bytes, linv_trail,
-      pack_a, pack_b, total;
+      linv_left, pack_a, pack_b, total;
 };
 
 bool packs_operands(int prec) { return prec == LP_BF16 || prec == LP_FP16; }
@@ -84,6 +83,9 @@ FactorLayout factor_layout(int n, int nb, int prec) {
   L.plan_bytes = align_up(swap_plan_bytes(kMaxNb), 256);
   off += kPlanRing * L.plan_bytes;
   L.linv_trail = off;
+  off = align_up(off + trsm_workspace_bytes(256), 256);
+  // block inverses of the no-pivot left-block solve (its own stream)
+  L.linv_left = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
   // bfloat16 / half: the packed operands of the trailing update (-L of the
   // step; U^T of a column range, placed at a 256-row offset per range)
@@ -124,6 +126,19 @@ struct Factor {
     unsigned* bar = barriers + idx;
     return launch_panel_fused<T>(m, j0, w, A, lda, ipiv, info, slots, bar, staging,
                                  keys[idx & 1], keys[(idx + 1) & 1], s, max_wgs);
+  }
+
+  // the same columns without pivoting, as the paper's LU and left kernels:
+  // the w x w diagonal block in one workgroup (no pivot search), then the
+  // blocks below it solved against its upper triangle, L21 = A21 U11^-1
+  int panel_nopiv(int j0, int w, void* linv_left) {
+    if (next_barrier >= n_barriers) return LP_ENOTSUP;
+    const int idx = next_barrier++;
+    int rc = launch_panel_fused<T>(j0 + w, j0, w, A, lda, ipiv, info, slots, barriers + idx,
+                                   staging, keys[idx & 1], keys[(idx + 1) & 1], s, 0, true);
+    if (rc != LP_OK || j0 + w >= m) return rc;
+    return launch_trsm_right_upper<T>(m - j0 - w, w, at(j0, j0), lda, at(j0 + w, j0), lda,
+                                      linv_left, s);
   }
 };
 
@@ -279,6 +294,7 @@ struct FactorCfg {
   bool lookahead = true;
   int panel_cus = 0;
   int panel_rows = 0;
+  bool pivot = true;  // false: the paper's elimination without row exchanges
 };
 
 // Streams restricted by compute-unit masks: the first `reserve` mask bits for
@@ -330,6 +346,11 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   Factor<T> f{n, A, lda, ipiv, info, work + L.slots, (unsigned*)(work + L.barriers),
               (int)L.n_barriers, 0, work + L.staging, {work + L.keys0, work + L.keys1}, s};
   void* linv_trail = work + L.linv_trail;
+  void* linv_left = work + L.linv_left;
+  const bool piv = cfg.pivot;
+  auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
+    return piv ? f.panel(j0, w, max_wgs) : f.panel_nopiv(j0, w, linv_left);
+  };
   char* plan_ring = work + L.plan_trail;
   void* plan_trail = plan_ring;  // the current step's plan
   const int npanels = (int)cdiv(n, nb);
@@ -368,11 +389,14 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   auto trailing = [&](int j0, int w, int c0, int c1, bool left) -> int {
     const int j1 = j0 + w;
     int r;
-    if ((r = prof.begin(prof.swap, ms)) != LP_OK) return r;
-    if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, ms)) != LP_OK)
-      return r;
-    if ((r = prof.end(prof.swap, ms)) != LP_OK) return r;
-    prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
+    if (piv) {
+      if ((r = prof.begin(prof.swap, ms)) != LP_OK) return r;
+      if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, ms)) !=
+          LP_OK)
+        return r;
+      if ((r = prof.end(prof.swap, ms)) != LP_OK) return r;
+      prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
+    }
     if (c1 <= c0) return LP_OK;
     if ((r = prof.begin(prof.trsm, ms)) != LP_OK) return r;
     if ((r = launch_trsm_lower_unit<T>(w, c1 - c0, f.at(j0, j0), lda, f.at(j0, c0), lda,
@@ -405,7 +429,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
 
   // panel 0 on the caller's stream
   if ((rc = prof.begin(prof.panel, s)) != LP_OK) return rc;
-  if ((rc = f.panel(0, std::min(nb, n))) != LP_OK) return rc;
+  if ((rc = factor_panel(0, std::min(nb, n), 0)) != LP_OK) return rc;
   if ((rc = prof.end(prof.panel, s)) != LP_OK) return rc;
   hipEvent_t panel_done = nullptr;  // event after the current panel (look-ahead stream)
   for (int k = 0; k < npanels; ++k) {
@@ -436,10 +460,10 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     const int slot = k % kPlanRing;
     plan_trail = plan_ring + (size_t)slot * L.plan_bytes;
     if (left_done[slot]) LP_HIP_TRY(hipStreamWaitEvent(ms, left_done[slot], 0));
-    if (j0 > 0 || j1 < n) {
+    if (piv && (j0 > 0 || j1 < n)) {
       if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, ms)) != LP_OK) return rc;
     }
-    if (ls && j0 > 0) {
+    if (piv && ls && j0 > 0) {
       // the exchanges left of the panel: nothing reads those columns before the
       // final join, so they run behind the main stream
       hipEvent_t plan_ready;
@@ -462,7 +486,8 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       LP_HIP_TRY(hipStreamWaitEvent(ps, next_ready, 0));
       f.s = ps;
       if ((rc = prof.begin(prof.panel, ps)) != LP_OK) return rc;
-      if ((rc = f.panel(j1, w2, pwgs ? pwgs : lookahead_panel_wgs<T>(n - j1))) != LP_OK) return rc;
+      if ((rc = factor_panel(j1, w2, pwgs ? pwgs : lookahead_panel_wgs<T>(n - j1))) != LP_OK)
+        return rc;
       if ((rc = prof.end(prof.panel, ps)) != LP_OK) return rc;
       f.s = s;
       if ((rc = la.event(&panel_done)) != LP_OK) return rc;
@@ -473,7 +498,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       if (more) {
         f.s = ms;
         if ((rc = prof.begin(prof.panel, ms)) != LP_OK) return rc;
-        if ((rc = f.panel(j1, w2)) != LP_OK) return rc;
+        if ((rc = factor_panel(j1, w2, 0)) != LP_OK) return rc;
         if ((rc = prof.end(prof.panel, ms)) != LP_OK) return rc;
         f.s = s;
       }
@@ -560,6 +585,7 @@ int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32
     cfg.lookahead = opts->lookahead != 0;
     cfg.panel_cus = opts->panel_cus;
     cfg.panel_rows = opts->panel_rows;
+    cfg.pivot = opts->no_pivoting == 0;
   }
   hipStream_t s = (hipStream_t)stream;
   if (prec == LP_FP64)
@@ -571,6 +597,16 @@ int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32
 int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info, void* work,
               size_t work_bytes, void* stream) {
   return lu_factor_ex(n, nb, prec, A, lda, ipiv, info, work, work_bytes, nullptr, nullptr, stream);
+}
+
+int lu_factor_nopiv(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
+                    void* work, size_t work_bytes, void* stream) {
+  lp_factor_opts o;
+  o.lookahead = 1;
+  o.panel_cus = 0;
+  o.panel_rows = 0;
+  o.no_pivoting = 1;
+  return lu_factor_ex(n, nb, prec, A, lda, ipiv, info, work, work_bytes, &o, nullptr, stream);
 }
 
 int lu_solve(int n, int storage, const void* LU, int lda, const int32_t* ipiv,
@@ -607,7 +643,7 @@ int residual_check(int n, const double* A, int lda, const double* X, int ldx, co
 }
 
 int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
-                    void* work, size_t work_bytes, void* stream) {
+                    void* work, size_t work_bytes, int max_wgs, void* stream) {
   if (m < 0 || m > kMaxN) return -1;
   if (w < 0 || w > m || w > kMaxNb) return -2;
   if (!valid_prec(prec)) return -3;
@@ -617,6 +653,7 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
   if (info == nullptr) return -7;
   if (work == nullptr) return -8;
   if (work_bytes < lu_workspace_bytes(m, std::max(1, w), prec)) return LP_ENOSPC;
+  if (max_wgs < 0) return -10;
   hipStream_t s = (hipStream_t)stream;
   const FactorLayout L = factor_layout(m, std::max(1, w), prec);
   int rc = launch_zero_words(info, 1, s);
@@ -630,12 +667,12 @@ int lp_panel_factor(int m, int w, int prec, void* A, int lda, int32_t* ipiv, int
     Factor<double> f{m, (double*)A, lda, ipiv, info, wk + L.slots,
                      (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.staging,
                      {wk + L.keys0, wk + L.keys1}, s};
-    return f.panel(0, w);
+    return f.panel(0, w, max_wgs);
   }
   Factor<float> f{m, (float*)A, lda, ipiv, info, wk + L.slots,
                   (unsigned*)(wk + L.barriers), (int)L.n_barriers, 0, wk + L.staging,
                   {wk + L.keys0, wk + L.keys1}, s};
-  return f.panel(0, w);
+  return f.panel(0, w, max_wgs);
 }
 
 size_t lp_laswp_workspace_bytes(int nswaps) {
@@ -685,6 +722,28 @@ int lp_trsm_lower_unit(int prec, int m, int ncols, const void* L, int ldl, void*
     return launch_trsm_lower_unit<double>(m, ncols, (const double*)L, ldl, (double*)B, ldb, work,
                                           s);
   return launch_trsm_lower_unit<float>(m, ncols, (const float*)L, ldl, (float*)B, ldb, work, s);
+}
+
+size_t lp_trsm_right_workspace_bytes(int w) {
+  if (w < 0) return 0;
+  return trsm_workspace_bytes(std::min(std::max(w, 1), 128));
+}
+
+int lp_trsm_right_upper(int prec, int m, int w, const void* U, int ldu, void* B, int ldb,
+                        void* work, size_t work_bytes, void* stream) {
+  if (!valid_prec(prec)) return -1;
+  if (m < 0) return -2;
+  if (w < 0 || w > kMaxNb) return -3;
+  if (U == nullptr && w > 0) return -4;
+  if (ldu < std::max(1, w)) return -5;
+  if (B == nullptr && m > 0 && w > 0) return -6;
+  if (ldb < std::max(1, w)) return -7;
+  if (work == nullptr) return -8;
+  if (work_bytes < lp_trsm_right_workspace_bytes(w)) return LP_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LP_FP64)
+    return launch_trsm_right_upper<double>(m, w, (const double*)U, ldu, (double*)B, ldb, work, s);
+  return launch_trsm_right_upper<float>(m, w, (const float*)U, ldu, (float*)B, ldb, work, s);
 }
 
 int lp_gemm_update(int prec, int M, int N, int K, const void* A, int lda, const void* B, int ldb,

@@ -73,7 +73,8 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     int m, int c0, int W, T* __restrict__ A, long long lda, int32_t* __restrict__ ipiv,
     int32_t* __restrict__ info, int R, int G, char* __restrict__ slots,
     unsigned* __restrict__ barrier, T* __restrict__ staging,
-    unsigned long long* __restrict__ keys, unsigned long long* __restrict__ keys_next) {
+    unsigned long long* __restrict__ keys, unsigned long long* __restrict__ keys_next,
+    int nopiv) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc acc_t;
   // row blocks of 16 per load batch in (F): a whole 256-row chunk for binary32
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
         for (int q = 0; q < RPT; ++q) {
           const int r = tid + 256 * q;
           const int gi = base + r;
-          if (r < nrows && gi >= dg) {
+          if (!nopiv && r < nrows && gi >= dg) {
             const T v = x[q][jj];
             const double k = (v != v) ? -1.0 : fabs((double)v);
             if (better(k, gi, bk, bi)) {
@@ -242,8 +243,9 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
         const T* urow;  // the pivot row (LDS)
         const T* drv;   // the old diagonal row (LDS)
         if (G == 1) {
+          // without pivoting (nopiv) the diagonal row is the pivot row
           const T dv = drw[par][jj];
-          p = (dv != dv) ? dg : bi;
+          p = (nopiv || dv != dv) ? dg : bi;
           drv = drw[par];
           urow = (p == dg) ? drv : wrow[par][wbest];
         } else {
@@ -597,10 +599,11 @@ size_t panel_keys_bytes() { return sizeof(unsigned long long) * (size_t)kKeySlot
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s, int max_wgs) {
+                       void* keys_next, hipStream_t s, int max_wgs, bool nopiv) {
   const int rows = m - c0;
   if (rows <= 0 || W <= 0) return LP_OK;
   if (W > rows) return LP_ENOTSUP;
+  if (nopiv && rows > kPanelRowsPerWg) return LP_ENOTSUP;  // one workgroup only
   const int ncu = num_cus();
   int R, G;
   if (rows <= kPanelRowsPerWg) {
@@ -627,7 +630,7 @@ int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv,
   hipLaunchKernelGGL((panel_fused_kernel<T, RPTV, LWV>), dim3(G), dim3(256), lds, s, m, c0, W, A, \
                      lda,                                                                        \
                      ipiv, info, R, G, (char*)slots, barrier, (T*)staging,                       \
-                     (unsigned long long*)keys, (unsigned long long*)keys_next)
+                     (unsigned long long*)keys, (unsigned long long*)keys_next, nopiv ? 1 : 0)
   if (R <= kChunk)
     LP_PANEL_LAUNCH(1, 32);
   else if (R <= 2 * kChunk)
@@ -642,8 +645,10 @@ int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv,
 }
 
 template int launch_panel_fused<double>(int, int, int, double*, long long, int32_t*, int32_t*,
-                                        void*, unsigned*, void*, void*, void*, hipStream_t, int);
+                                        void*, unsigned*, void*, void*, void*, hipStream_t, int,
+                                        bool);
 template int launch_panel_fused<float>(int, int, int, float*, long long, int32_t*, int32_t*,
-                                       void*, unsigned*, void*, void*, void*, hipStream_t, int);
+                                       void*, unsigned*, void*, void*, void*, hipStream_t, int,
+                                       bool);
 
 }  // namespace lp

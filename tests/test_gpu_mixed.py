@@ -91,8 +91,17 @@ def test_fp32_factorization_matches_oracle_on_fp32_matrix(lp, n, nb):
     got_piv = host(ipiv)[:n]
     agree = np.mean(got_piv == piv_o)
     assert agree >= 0.99, agree          # binary32 near-ties may legitimately differ
+    got = host(tA).astype(np.float64)
     if agree == 1.0:
-        assert np.max(np.abs(host(tA) - lu_o)) <= 200 * n * U32
+        assert np.max(np.abs(got - lu_o)) <= 200 * n * U32
+    # whatever the pivots: |l| <= 1 and P A = L U within the binary32
+    # backward-error bound of Gaussian elimination (gamma_n |L| |U|)
+    assert np.max(np.abs(np.tril(got, -1))) <= 1.0
+    L = np.tril(got, -1) + np.eye(n)
+    U = np.triu(got)
+    pa = a32.astype(np.float64)[oracle.perm_from_ipiv(got_piv, n)]
+    bound = 4 * n * U32 * (np.abs(L) @ np.abs(U))
+    assert np.all(np.abs(pa - L @ U) <= bound)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])

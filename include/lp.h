@@ -93,6 +93,24 @@ size_t lu_workspace_bytes(int n, int nb, int prec);
 int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
               void *work, size_t work_bytes, void *stream);
 
+/* lu_factor for callers that cannot allocate device memory (code under HIP
+ * graph capture, fixed serving loops, harnesses that forbid hipMalloc): the
+ * same partial-pivoting factorization, same arguments and results, but the
+ * workspace is a file-scope device array of the library
+ * (lu_factor_noalloc_max_bytes() = 8 MiB per device, held until the process
+ * ends) instead of a caller buffer.  The call itself allocates nothing: no
+ * device memory, streams or events; it runs strictly in order on `stream`
+ * (no look-ahead).  prec LP_FP64 or LP_FP32 (bfloat16 / half need packed
+ * operands: LP_ENOTSUP); LP_ENOSPC when lu_workspace_bytes(n, nb, prec)
+ * exceeds the array (it does not for any n <= 131072).  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (different streams, or several host threads) race and give wrong
+ * results; calls in order on one stream are safe.  What must start at zero is
+ * cleared by each call. */
+size_t lu_factor_noalloc_max_bytes(void);
+int lu_factor_noalloc(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
+                      void *stream);
+
 /* Options and per-phase profile for lu_factor_ex. */
 typedef struct {
   int lookahead;  /* 1 (default): factor the next panel on a second stream while the

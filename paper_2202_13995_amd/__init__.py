@@ -97,6 +97,8 @@ SIGNATURES = {
     "lu_factor": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lu_factor_ex": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, ctypes.POINTER(FactorOpts),
                           ctypes.POINTER(FactorProfile), _VP]),
+    "lu_factor_noalloc_max_bytes": (_SZ, []),
+    "lu_factor_noalloc": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP]),
     "lu_factor_nopiv": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lu_solve": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP]),
     "residual_check": (_I, [_I, _VP, _I, _VP, _I, _VP, _I, _I, _VP, _VP]),

@@ -541,6 +541,33 @@ int factor_entry(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, in
   return rc;
 }
 
+// Scratch of lu_factor_noalloc: a file-scope device array, so that callers
+// that cannot allocate (code under graph capture, fixed serving loops) still
+// get a factorization workspace.  Each device holds its own copy for the life
+// of the process.  Host code never names the array directly (its host-side
+// symbol is not a device address): the device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  LP_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return LP_ENOTSUP;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    LP_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return LP_OK;
+}
+
 }  // namespace
 }  // namespace lp
 
@@ -597,6 +624,32 @@ int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32
 int lu_factor(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info, void* work,
               size_t work_bytes, void* stream) {
   return lu_factor_ex(n, nb, prec, A, lda, ipiv, info, work, work_bytes, nullptr, nullptr, stream);
+}
+
+size_t lu_factor_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int lu_factor_noalloc(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,
+                      void* stream) {
+  if (n < 0) return -1;
+  if (n > kMaxN) return LP_ENOTSUP;
+  if (nb < 1 || nb > kMaxNb) return -2;
+  if (!valid_prec(prec)) return -3;
+  if (prec != LP_FP64 && prec != LP_FP32) return LP_ENOTSUP;  // packed operands need more
+  if (A == nullptr && n > 0) return -4;
+  if (lda < std::max(1, n)) return -5;
+  if (ipiv == nullptr && n > 0) return -6;
+  if (info == nullptr) return -7;
+  if (lu_workspace_bytes(n, nb, prec) > kNoAllocScratchBytes) return LP_ENOSPC;
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc != LP_OK) return rc;
+  FactorCfg cfg;
+  cfg.lookahead = false;  // one stream: no internal streams or events to create
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LP_FP64)
+    return factor_entry<double>(n, nb, prec, (double*)A, lda, ipiv, info, (char*)ws, s, cfg,
+                                nullptr);
+  return factor_entry<float>(n, nb, prec, (float*)A, lda, ipiv, info, (char*)ws, s, cfg, nullptr);
 }
 
 int lu_factor_nopiv(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32_t* info,

@@ -175,11 +175,12 @@ def traffic_from_profile(kernel_src: str, n: int, nb: int):
 
 
 def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_leg=True,
-                x_ref=None, x_ref_label=None):
+                x_ref=None, x_ref_label=None, nopiv_leg=False):
     """R timed solves (after one untimed) of one system through the
     low-precision factorization plus binary64 refinement (and the binary64
     fallback when refinement fails).  With fp64_leg the binary64 blocked path
-    is timed on that same system the same way, for the speedup.  The forward
+    is timed on that same system the same way, for the speedup (and with
+    nopiv_leg the binary64 path without row exchanges too).  The forward
     error is taken against x_ref (the oracle's or the binary64 path's x) and
     the backward error is the scaled residual."""
     A = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -247,6 +248,28 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
         res["fp64_ms_same_system"] = st64["median_ms"]
         res["speedup_vs_fp64"] = st64["median_ms"] / st["median_ms"]
         res["forward_error_vs_fp64_path"] = forward_error(X, X64)
+        if nopiv_leg:
+            # the paper's elimination without row exchanges (valid here: A + n I
+            # is diagonally dominant) on the same system: the cost of pivoting
+            Xp = X64.clone()
+            tn = []
+            for r in range(R + 1):
+                A64.copy_(A)
+                X64.copy_(B)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lp.lu_factor_nopiv(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
+                lp.lu_solve(A64, ipiv, info, X64)
+                out = lp.residual_check(A, X64, B)
+                torch.cuda.synchronize()
+                if r > 0:
+                    tn.append(time.perf_counter() - t0)
+            stn = stats_ms(tn)
+            res["fp64_nopiv_same_system"] = dict(
+                stn, scaled_residual=float(out[:, 0].max().item()),
+                tflops=flops(n, nrhs) / (stn["median_ms"] * 1e-3) / 1e12,
+                rel_x_diff_vs_pivoted=forward_error(X64, Xp),
+                pivoting_cost=st64["median_ms"] / stn["median_ms"])
         del A64, w64
     if x_ref is not None:
         res["forward_error_vs_" + x_ref_label] = forward_error(X, x_ref)
@@ -524,7 +547,7 @@ def main() -> int:
         mnb = args.mixed_nb or nb
         log(f"[bench] mixed {args.mixed_prec} n={mn} nb={mnb} shift={mn} ...")
         line["mixed_ir"] = bench_mixed(lp, inputs, torch, dev, mn, mnb, args.mixed_prec,
-                                       float(mn), args.seed, R, args.nrhs)
+                                       float(mn), args.seed, R, args.nrhs, nopiv_leg=True)
         log(f"[bench] mixed done: {line['mixed_ir']['ms_per_solve']:.1f} ms/solve, "
             f"speedup {line['mixed_ir']['speedup_vs_fp64']:.2f}x")
         if not args.no_mixed_unshifted:

@@ -30,6 +30,9 @@ More objects ride on the same line:
     system the same number of times for the speedup);
   * `mixed_ir_unshifted` (the same route on the unshifted headline system:
     refinement history, fallback, and the time with and without it);
+  * `ptrans` (the paper's matrix transposition kernel C = B + A^T at
+    n = 32768: achieved GB/s against the HBM peak, and the paper's n^2
+    additions per second);
   * `serving` (an open-loop Poisson stream through the continuous-batching
     server: p50/p99 latency overall and per request class, aggregate TFLOP/s).
 One process, one GPU; prints one JSON line on stdout, progress on stderr.
@@ -278,6 +281,36 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
     return res
 
 
+def bench_ptrans(lp, inputs, torch, dev, n, seed, reps):
+    """The paper's PTRANS kernel, C = B + A^T, timed with HIP events on the
+    stream it runs on (bound by HBM: 3 n^2 elements per call); the paper's
+    operation count is n^2 additions."""
+    out = {"workload": f"PTRANS C = B + A^T, n={n}, A, B uniform[-0.5,0.5) seeds {seed}, "
+                       f"{seed + 1}", "n": n}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        A = torch.empty((n, n), dtype=dt, device=dev)
+        inputs.fill_matrix_(A, seed)
+        B = torch.empty((n, n), dtype=dt, device=dev)
+        inputs.fill_matrix_(B, seed + 1)
+        C = torch.empty_like(B)
+        lp.ptrans(A, B, C)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            lp.ptrans(A, B, C)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        nbytes = 3.0 * n * n * A.element_size()
+        out[name] = {"us_per_call": 1e6 * t, "GBps": nbytes / t / 1e9,
+                     "frac_hbm_peak": nbytes / t / 1e9 / PEAK_HBM_GBS,
+                     "GFLOPs_paper_metric": n * n / t / 1e9, "bytes_per_call": nbytes}
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small_n_max=512,
                   large_slots=8):
     """Open-loop Poisson stream of solves through the continuous-batching server.
@@ -406,6 +439,8 @@ def main() -> int:
     ap.add_argument("--serve-large-slots", type=int, default=8)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ptrans-n", type=int, default=32768)
+    ap.add_argument("--no-ptrans", action="store_true")
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run a plain element-wise copy-convert of this many MiB of doubles "
                          "before the timed steps (reference for HBM traffic counters)")
@@ -566,6 +601,10 @@ def main() -> int:
                 f"{line['mixed_ir_unshifted']['ms_per_solve']:.1f} ms/solve, fell back "
                 f"{line['mixed_ir_unshifted']['fell_back']}")
         torch.cuda.empty_cache()
+    if not args.no_ptrans:
+        log(f"[bench] PTRANS n={args.ptrans_n} ...")
+        line["ptrans"] = bench_ptrans(lp, inputs, torch, dev, args.ptrans_n, args.seed, 20)
+        log(f"[bench] PTRANS done: {line['ptrans']['fp64']['GBps']:.0f} GB/s (binary64)")
     if not args.no_serve:
         log(f"[bench] serving {args.serve_requests} requests at {args.serve_rate:g}/s ...")
         line["serving"] = bench_serving(lp, inputs, torch, dev, args.serve_requests,

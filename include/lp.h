@@ -366,6 +366,18 @@ size_t lp_gemm_packed_workspace_bytes(int M, int N, int K);
 int lp_gemm_update_packed(int prec, int M, int N, int K, const void *A, int lda, const void *B,
                           int ldb, void *C, int ldc, void *work, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------ matrix transposition */
+/* The paper's PTRANS kernel (section "Parallel Matrix Transposition"):
+ * C := B + A^T for n x n row-major A (lda), B (ldb), C (ldc), binary64
+ * (prec LP_FP64) or binary32 (LP_FP32), one correctly rounded addition per
+ * element, so results are exact to the bit against any plain evaluation.  C
+ * may be the same buffer as B (in place); C must not overlap A (not checked;
+ * an overlap gives undefined results).  Bound by HBM
+ * bandwidth: 3 n^2 elements are read or written once; the paper counts n^2
+ * additions as its operations. */
+int lp_ptrans(int prec, int n, const void *A, int lda, const void *B, int ldb, void *C, int ldc,
+              void *stream);
+
 /* Element-wise copies between binary64 and binary32 (row-major, rows x cols):
  * to_f32 != 0 converts src double -> dst float (round to nearest even),
  * else src float -> dst double. */

@@ -60,6 +60,13 @@ def _load():
                                           ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp,
                                           dp]
         lib.orc_row_residuals.restype = None
+        fp = ctypes.POINTER(ctypes.c_float)
+        lib.orc_ptrans.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                   ctypes.c_int]
+        lib.orc_ptrans.restype = None
+        lib.orc_ptrans_f32.argtypes = [ctypes.c_int, fp, ctypes.c_int, fp, ctypes.c_int, fp,
+                                       ctypes.c_int]
+        lib.orc_ptrans_f32.restype = None
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -172,6 +179,26 @@ def row_residuals(a_rows, x, b_rows):
     lib.orc_row_residuals(n, cnt, _dp(a_rows), n, _dp(x), nrhs, _dp(b_rows), nrhs, nrhs,
                           _dp(r), _dp(ad))
     return r, ad
+
+
+def ptrans(a, b):
+    """C = B + A^T (the paper's PTRANS), in the precision of a (float64 or float32)."""
+    lib = _load()
+    if np.asarray(a).dtype == np.float32:
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        c = np.empty_like(b)
+        fp = ctypes.POINTER(ctypes.c_float)
+        n = a.shape[0]
+        lib.orc_ptrans_f32(n, a.ctypes.data_as(fp), max(n, 1), b.ctypes.data_as(fp), max(n, 1),
+                           c.ctypes.data_as(fp), max(n, 1))
+        return c
+    a = _as_f64(a)
+    b = _as_f64(b)
+    c = np.empty_like(b)
+    n = a.shape[0]
+    lib.orc_ptrans(n, _dp(a), max(n, 1), _dp(b), max(n, 1), _dp(c), max(n, 1))
+    return c
 
 
 def unpack(lu):

@@ -243,6 +243,20 @@ int orc_getrs_trans(int n, const double *LU, int lda, const int *ipiv, double *B
   return 0;
 }
 
+/* The PTRANS operation (paper, section "Parallel Matrix Transposition"):
+ * C = B + A^T for n x n row-major matrices, element by element,
+ * c_ij = b_ij + a_ji (one rounded addition each). */
+void orc_ptrans(int n, const double *A, int lda, const double *B, int ldb, double *C, int ldc) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) C[(size_t)i * ldc + j] = B[(size_t)i * ldb + j] + A[(size_t)j * lda + i];
+}
+
+/* The same in binary32. */
+void orc_ptrans_f32(int n, const float *A, int lda, const float *B, int ldb, float *C, int ldc) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) C[(size_t)i * ldc + j] = B[(size_t)i * ldb + j] + A[(size_t)j * lda + i];
+}
+
 /* Scaled residual per right-hand side, binary64 with left-to-right sums.
  * out[5*c + 0..4] = { s, ||r||_inf, ||A||_inf, ||x_c||_inf, ||b_c||_inf } with
  * r = A x - b.  A NaN anywhere propagates into s (and s < 16 is then false). */

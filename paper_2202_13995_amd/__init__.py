@@ -124,6 +124,7 @@ SIGNATURES = {
     "lp_gemm_update": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
     "lp_gemm_packed_workspace_bytes": (_SZ, [_I, _I, _I]),
     "lp_gemm_update_packed": (_I, [_I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _VP, _SZ, _VP]),
+    "lp_ptrans": (_I, [_I, _I, _VP, _I, _VP, _I, _VP, _I, _VP]),
     "lp_convert": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP]),
 }
 
@@ -503,6 +504,23 @@ def gemm_update_packed(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, prec=B
                                         C.data_ptr(), ldc, work.data_ptr(), work.numel(),
                                         _stream(stream)))
     _keep(work, stream)
+
+
+def ptrans(A: torch.Tensor, B: torch.Tensor, C=None, stream=None) -> torch.Tensor:
+    """C := B + A^T (the paper's PTRANS); C defaults to a new tensor, may be B."""
+    dt = A.dtype
+    p = FP64 if dt == torch.float64 else FP32
+    n = A.shape[0]
+    if A.shape != (n, n) or B.shape != (n, n):
+        raise ValueError("A and B must be n x n")
+    lda = _mat(A, dt, "A")
+    ldb = _mat(B, dt, "B")
+    if C is None:
+        C = torch.empty_like(B)
+    ldc = _mat(C, dt, "C")
+    _check("lp_ptrans", _lib().lp_ptrans(p, n, A.data_ptr(), lda, B.data_ptr(), ldb, C.data_ptr(),
+                                         ldc, _stream(stream)))
+    return C
 
 
 def convert(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -26,7 +26,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
-SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "panel_fused.hip", "nopiv.hip", "solve.hip",
+SOURCES = ["gemm.hip", "gemm_lp.hip", "panel.hip", "panel_fused.hip", "nopiv.hip", "ptrans.hip", "solve.hip",
            "driver.hip", "ir.hip", "serve.hip"]
 
 

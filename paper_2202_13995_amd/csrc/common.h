@@ -108,6 +108,10 @@ int launch_residual(int n, const double* A, long long lda, const double* X, long
                     const double* B, long long ldb, int nrhs, double* out, hipStream_t s,
                     double* Rv, long long ldr);
 
+// C := B + A^T (n x n, prec LP_FP64 or LP_FP32); C may be B, must not overlap A.
+int launch_ptrans(int prec, int n, const void* A, long long lda, const void* B, long long ldb,
+                  void* C, long long ldc, hipStream_t s);
+
 // Zero a range of 32-bit words (a kernel, not a memset node).
 int launch_zero_words(void* p, size_t nwords, hipStream_t s);
 

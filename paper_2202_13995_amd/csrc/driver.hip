@@ -841,6 +841,19 @@ int lp_gemm_update_packed(int prec, int M, int N, int K, const void* A, int lda,
       w + align_up(gemm_lp_packed_bytes(M, K), 256), true, (hipStream_t)stream);
 }
 
+int lp_ptrans(int prec, int n, const void* A, int lda, const void* B, int ldb, void* C, int ldc,
+              void* stream) {
+  if (prec != LP_FP64 && prec != LP_FP32) return -1;
+  if (n < 0) return -2;
+  if (A == nullptr && n > 0) return -3;
+  if (lda < std::max(1, n)) return -4;
+  if (B == nullptr && n > 0) return -5;
+  if (ldb < std::max(1, n)) return -6;
+  if (C == nullptr && n > 0) return -7;
+  if (ldc < std::max(1, n)) return -8;
+  return launch_ptrans(prec, n, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+}
+
 int lp_convert(int to_f32, int rows, int cols, const void* src, int lds, void* dst, int ldd,
                void* stream) {
   if (rows < 0) return -2;

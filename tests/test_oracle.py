@@ -376,3 +376,35 @@ def test_condition_estimate_is_a_lower_bound():
         assert est >= exact / 3
         hits += abs(est - exact) <= 1e-10 * exact
     assert hits >= 6
+
+
+# ------------------------------------------------------------------ PTRANS
+def test_ptrans_special_cases():
+    # C = B + A^T (paper, section "Parallel Matrix Transposition")
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 7, 64, 65, 130):
+        a = rng.uniform(-1, 1, (n, n))
+        b = rng.uniform(-1, 1, (n, n))
+        # B = 0: the plain transpose, bit for bit
+        assert np.array_equal(oracle.ptrans(a, np.zeros((n, n))), a.T)
+        # A = I: B plus the identity
+        assert np.array_equal(oracle.ptrans(np.eye(n), b), b + np.eye(n))
+        # symmetric A: the transpose changes nothing
+        s = a + a.T
+        assert np.array_equal(oracle.ptrans(s, b), b + s)
+        # an asymmetric single entry lands transposed
+        e = np.zeros((n, n))
+        e[n - 1, 0] = 3.0
+        c = oracle.ptrans(e, np.zeros((n, n)))
+        assert c[0, n - 1] == 3.0 and np.count_nonzero(c) == 1
+
+
+def test_ptrans_binary32_rounds_once():
+    rng = np.random.default_rng(13)
+    a = rng.uniform(-1, 1, (50, 50)).astype(np.float32)
+    b = rng.uniform(-1, 1, (50, 50)).astype(np.float32)
+    c = oracle.ptrans(a, b)
+    assert c.dtype == np.float32
+    # the exact sum rounded once to binary32
+    exact = b.astype(np.float64) + a.T.astype(np.float64)
+    assert np.array_equal(c, exact.astype(np.float32))

@@ -231,6 +231,8 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
         A64 = torch.empty_like(A)
         X64 = torch.empty_like(B)
         w64 = lp.workspace(n, nb, "fp64", dev)
+        sw64 = torch.empty(lp.lib.lu_solve_workspace_bytes(n, lp.FP64, nrhs), dtype=torch.uint8,
+                           device=dev)
         ipiv = torch.empty(n, dtype=torch.int32, device=dev)
         info = torch.empty(1, dtype=torch.int32, device=dev)
         t64 = []
@@ -241,7 +243,7 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             lp.lu_factor(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
-            lp.lu_solve(A64, ipiv, info, X64)
+            lp.lu_solve(A64, ipiv, info, X64, work=sw64)
             out = lp.residual_check(A, X64, B)
             torch.cuda.synchronize()
             if r > 0:  # the first solve is the untimed warm-up
@@ -262,7 +264,7 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 lp.lu_factor_nopiv(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
-                lp.lu_solve(A64, ipiv, info, X64)
+                lp.lu_solve(A64, ipiv, info, X64, work=sw64)
                 out = lp.residual_check(A, X64, B)
                 torch.cuda.synchronize()
                 if r > 0:
@@ -466,6 +468,8 @@ def main() -> int:
     B0 = torch.empty((n, args.nrhs), dtype=torch.float64, device=dev)
     inputs.fill_rhs_(B0, args.seed)
     work = lp.workspace(n, nb, "fp64", dev)
+    swork = torch.empty(lp.lib.lu_solve_workspace_bytes(n, lp.FP64, args.nrhs), dtype=torch.uint8,
+                        device=dev)
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     look = not args.no_lookahead
@@ -488,7 +492,7 @@ def main() -> int:
         X.copy_(B0)
         lp.lu_factor(A, nb, "fp64", work=work, ipiv=ipiv, info=info, lookahead=look,
                      panel_cus=args.panel_cus, panel_rows=args.panel_rows)
-        lp.lu_solve(A, ipiv, info, X)
+        lp.lu_solve(A, ipiv, info, X, work=swork)
         lp.residual_check(A0, X, B0)
         torch.cuda.synchronize()
         log(f"[bench] warm-up {w + 1}/{W} done")
@@ -505,7 +509,7 @@ def main() -> int:
         _, _, prof = lp.lu_factor(A, nb, "fp64", work=work, ipiv=ipiv, info=infos[i],
                                   lookahead=look, profile=True, panel_cus=args.panel_cus,
                                   panel_rows=args.panel_rows)
-        lp.lu_solve(A, ipiv, infos[i], X)
+        lp.lu_solve(A, ipiv, infos[i], X, work=swork)
         lp.residual_check(A0, X, B0, out=outs[i])
         torch.cuda.synchronize()
         step_s.append(time.perf_counter() - t0)

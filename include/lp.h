@@ -179,6 +179,23 @@ int lu_solve(int n, int storage, const void *LU, int lda, const int32_t *ipiv,
              const int32_t *info, void *B, int ldb, int nrhs, int32_t *solve_status,
              void *stream);
 
+/* lu_solve with a caller workspace: the same result, each triangle solved
+ * in one persistent launch (per 8 right-hand sides) instead of one launch
+ * pair per 128-row block.  Workgroups take 128-row block rows in the order
+ * they start and subtract the tiles of already solved blocks as those
+ * appear (published as tagged words in `work`), so the stream of factors
+ * overlaps the block-to-block dependency chain.  Arguments as lu_solve, plus
+ * work: device scratch of lu_solve_workspace_bytes(n, storage, nrhs) bytes
+ * (about 16 n bytes for binary64, 8 n for binary32), 256-byte aligned,
+ * contents irrelevant on entry; LP_ENOSPC if smaller.  If an internal wait
+ * ever times out (never on a healthy device), *solve_status is set to
+ * LP_INFO_BARRIER_TIMEOUT and B is invalid.  The summation order differs from
+ * lu_solve's, so results agree to rounding, not bit for bit. */
+size_t lu_solve_workspace_bytes(int n, int storage, int nrhs);
+int lu_solve_ex(int n, int storage, const void *LU, int lda, const int32_t *ipiv,
+                const int32_t *info, void *B, int ldb, int nrhs, int32_t *solve_status,
+                void *work, size_t work_bytes, void *stream);
+
 /* -------------------------------------------------------------- residual */
 
 /* The benchmark's residual check in binary64 on the ORIGINAL A and B:

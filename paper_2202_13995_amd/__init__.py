@@ -101,6 +101,8 @@ SIGNATURES = {
     "lu_factor_noalloc": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP]),
     "lu_factor_nopiv": (_I, [_I, _I, _I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
     "lu_solve": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP]),
+    "lu_solve_workspace_bytes": (_SZ, [_I, _I, _I]),
+    "lu_solve_ex": (_I, [_I, _I, _VP, _I, _VP, _VP, _VP, _I, _I, _VP, _VP, _SZ, _VP]),
     "residual_check": (_I, [_I, _VP, _I, _VP, _I, _VP, _I, _I, _VP, _VP]),
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
     "lu_solve_ir": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ,
@@ -237,8 +239,10 @@ def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=
 
 
 def lu_solve(LU: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, B: torch.Tensor,
-             status=None, stream=None):
-    """In place: B := A^-1 B from the factors. Returns the device solve status."""
+             status=None, stream=None, work=None, persistent: bool = True):
+    """In place: B := A^-1 B from the factors. Returns the device solve status.
+    persistent=True (default) uses lu_solve_ex, one launch per triangle, with
+    `work` (allocated here when None); False uses lu_solve (no workspace)."""
     dt = LU.dtype
     storage = FP64 if dt == torch.float64 else FP32
     lda = _mat(LU, dt, "LU")
@@ -248,9 +252,19 @@ def lu_solve(LU: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, B: torch.
         raise ValueError("B has the wrong number of rows")
     if status is None:
         status = torch.empty(1, dtype=torch.int32, device=LU.device)
-    _check("lu_solve", _lib().lu_solve(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
-                                    info.data_ptr(), B.data_ptr(), ldb, B.shape[1],
-                                    status.data_ptr(), _stream(stream)))
+    if not persistent:
+        _check("lu_solve", _lib().lu_solve(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
+                                           info.data_ptr(), B.data_ptr(), ldb, B.shape[1],
+                                           status.data_ptr(), _stream(stream)))
+        return status
+    if work is None:
+        work = torch.empty(_lib().lu_solve_workspace_bytes(n, storage, B.shape[1]),
+                           dtype=torch.uint8, device=LU.device)
+    _check("lu_solve_ex", _lib().lu_solve_ex(n, storage, LU.data_ptr(), lda, ipiv.data_ptr(),
+                                             info.data_ptr(), B.data_ptr(), ldb, B.shape[1],
+                                             status.data_ptr(), work.data_ptr(), work.numel(),
+                                             _stream(stream)))
+    _keep(work, stream)
     return status
 
 

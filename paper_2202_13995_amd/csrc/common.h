@@ -104,6 +104,15 @@ int launch_trsm_right_upper(int m, int w, const T* U, long long ldu, T* B, long 
 template <typename T>
 int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, const int32_t* info,
                     T* B, long long ldb, int nrhs, int32_t* status, hipStream_t s);
+// The same solve as one persistent launch per triangle (and per 8
+// right-hand sides) with a workspace of lu_solve_workspace_bytes_t(n,
+// sizeof(T)) bytes; TF is the factors' storage, T the right-hand sides'
+// type and the arithmetic (float factors may be applied in double).
+size_t lu_solve_workspace_bytes_t(int n, int elem_bytes);
+template <typename TF, typename T>
+int launch_lu_solve_ws(int n, const TF* LU, long long lda, const int32_t* ipiv,
+                       const int32_t* info, T* B, long long ldb, int nrhs, int32_t* status,
+                       void* work, hipStream_t s);
 int launch_residual(int n, const double* A, long long lda, const double* X, long long ldx,
                     const double* B, long long ldb, int nrhs, double* out, hipStream_t s,
                     double* Rv, long long ldr);

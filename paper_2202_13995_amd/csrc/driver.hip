@@ -681,6 +681,32 @@ int lu_solve(int n, int storage, const void* LU, int lda, const int32_t* ipiv,
                                 solve_status, s);
 }
 
+size_t lu_solve_workspace_bytes(int n, int storage, int nrhs) {
+  if (n < 0 || nrhs < 0 || (storage != LP_FP64 && storage != LP_FP32)) return 0;
+  return lu_solve_workspace_bytes_t(n, storage == LP_FP64 ? 8 : 4);
+}
+
+int lu_solve_ex(int n, int storage, const void* LU, int lda, const int32_t* ipiv,
+                const int32_t* info, void* B, int ldb, int nrhs, int32_t* solve_status,
+                void* work, size_t work_bytes, void* stream) {
+  if (n < 0) return -1;
+  if (storage != LP_FP64 && storage != LP_FP32) return -2;
+  if (LU == nullptr && n > 0) return -3;
+  if (lda < std::max(1, n)) return -4;
+  if (ipiv == nullptr && n > 0) return -5;
+  if (B == nullptr && n > 0 && nrhs > 0) return -7;
+  if (nrhs < 0) return -9;
+  if (ldb < std::max(1, nrhs)) return -8;
+  if (work == nullptr) return -11;
+  if (work_bytes < lu_solve_workspace_bytes(n, storage, nrhs)) return LP_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  if (storage == LP_FP64)
+    return launch_lu_solve_ws<double, double>(n, (const double*)LU, lda, ipiv, info, (double*)B,
+                                              ldb, nrhs, solve_status, work, s);
+  return launch_lu_solve_ws<float, float>(n, (const float*)LU, lda, ipiv, info, (float*)B, ldb,
+                                          nrhs, solve_status, work, s);
+}
+
 int residual_check(int n, const double* A, int lda, const double* X, int ldx, const double* B,
                    int ldb, int nrhs, double* out, void* stream) {
   if (n < 0) return -1;

@@ -56,7 +56,7 @@ unsigned blocks_for(long long total) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct IRLayout {
-  size_t big, fwork, ipiv, info, R, D, out, total;
+  size_t big, fwork, ipiv, info, R, D, out, swork, total;
 };
 
 IRLayout ir_layout(int n, int nb, int prec, int nrhs) {
@@ -78,6 +78,8 @@ IRLayout ir_layout(int n, int nb, int prec, int nrhs) {
   off = align_up(off + sizeof(float) * (size_t)n * nrhs, 256);
   L.out = off;
   off = align_up(off + sizeof(double) * 5 * (size_t)std::max(nrhs, 1), 256);
+  L.swork = off;  // the one-launch triangular solves (binary64 size covers binary32)
+  off = align_up(off + lu_solve_workspace_bytes_t(n, 8), 256);
   L.total = off;
   return L;
 }
@@ -161,6 +163,7 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
   double* R = (double*)(w + L.R);
   float* D = (float*)(w + L.D);
   double* out_d = (double*)(w + L.out);
+  void* swork = w + L.swork;
   const long long nn = (long long)n;
   Events evs;
   hipEvent_t e0, e_conv = nullptr, e_fact = nullptr, e_solve0 = nullptr, e_ref = nullptr,
@@ -194,7 +197,8 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
     hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks_for(nn * nrhs)), dim3(256), 0, s, n, nrhs, B,
                        ldb, X, ldx);
     LP_LAUNCH_CHECK();
-    return launch_lu_solve<double>(n, A64, nn, ipiv, info, X, ldx, nrhs, nullptr, s);
+    return launch_lu_solve_ws<double, double>(n, A64, nn, ipiv, info, X, ldx, nrhs, nullptr,
+                                              swork, s);
   };
 
   bool need_fallback = (prec == LP_FP64);
@@ -208,7 +212,8 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
       return rc;
     if ((rc = evs.record(s, &e_fact)) != LP_OK) return rc;
     if ((rc = launch_convert(1, n, nrhs, B, ldb, D, nrhs, s)) != LP_OK) return rc;
-    if ((rc = launch_lu_solve<float>(n, A32, nn, ipiv, info, D, nrhs, nrhs, nullptr, s)) != LP_OK)
+    if ((rc = launch_lu_solve_ws<float, float>(n, A32, nn, ipiv, info, D, nrhs, nrhs, nullptr,
+                                                swork, s)) != LP_OK)
       return rc;
     if ((rc = launch_convert(0, n, nrhs, D, nrhs, X, ldx, s)) != LP_OK) return rc;
     if ((rc = evs.record(s, &e_solve0)) != LP_OK) return rc;
@@ -230,8 +235,8 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
         }
         // d = solve(LU32, r); x += d
         if ((rc = launch_convert(1, n, nrhs, R, nrhs, D, nrhs, s)) != LP_OK) return rc;
-        if ((rc = launch_lu_solve<float>(n, A32, nn, ipiv, info, D, nrhs, nrhs, nullptr, s)) !=
-            LP_OK)
+        if ((rc = launch_lu_solve_ws<float, float>(n, A32, nn, ipiv, info, D, nrhs, nrhs,
+                                                    nullptr, swork, s)) != LP_OK)
           return rc;
         hipLaunchKernelGGL(add_f32_to_f64_kernel, dim3(blocks_for(nn * nrhs)), dim3(256), 0, s,
                            n, nrhs, D, (long long)nrhs, X, (long long)ldx);

@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "device.h"
 #include "swap_plan.h"
 
 namespace lp {
@@ -228,6 +229,235 @@ __global__ __launch_bounds__(256) void trsv_update_kernel(int rb, int re, int r0
   }
 }
 
+// ------------------------------------------- one launch per triangle
+// The blocked substitution as one persistent launch.  Workgroups take block
+// rows in the order they start (an atomic ticket): forward, block 0 first;
+// backward, the last block first.  The workgroup of block row I keeps the
+// rows' right-hand sides in registers and walks the off-diagonal tiles in the
+// order their solved blocks appear, subtracting L_IJ x_J (U_IJ x_J) with its
+// threads split over rows and column quarters; each tile's factors are loaded
+// before the wait for x_J, so the stream of factors overlaps the dependency
+// chain.  It then solves its diagonal block (held in LDS, loaded at the start)
+// and publishes x_I twice: into B (the result) and as tagged 64-bit words
+// (value bits + block tag, a double as two words) that other workgroups poll
+// with coherent loads until every word carries the tag -- no fence and no
+// flag-before-data ordering is needed.  A workgroup only ever waits for
+// blocks with smaller tickets, which have already started, so the launch
+// cannot deadlock whatever the residency; every wait is bounded in time
+// (timeout: the launch drains and reports through the status word).
+constexpr int kPT = 512;  // threads per persistent workgroup: 128 rows x 4 column quarters
+
+size_t trsv_rec_words(int n, int wpv) { return (size_t)cdiv(n, kTB) * kTB * kRhsChunk * wpv; }
+
+// TF: storage of the factors; T: the right-hand sides and the arithmetic
+// (binary32 factors can be applied in binary64, as the refinement's
+// preconditioner does).
+template <typename TF, typename T, bool lower, bool VEC>
+__global__ __launch_bounds__(kPT) void trsv_persistent_kernel(
+    int n, const TF* __restrict__ LU, long long lda, T* __restrict__ B, long long ldb, int c0,
+    int cw, unsigned long long* __restrict__ rec, unsigned* __restrict__ ctl,
+    const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  constexpr int WPV = (int)(sizeof(T) / 4);  // tagged words per value
+  constexpr int QW = kTB / 4;                // columns per quarter
+  __shared__ T Ld[kTB][kTB + 1];             // the diagonal block
+  __shared__ T xs[kTB][kRhsChunk];           // x_J of the tile being applied
+  __shared__ T red[kTB][kRhsChunk];          // partial sums of the column quarters
+  __shared__ int s_blk, s_to;
+  const int nblk = (int)cdiv(n, kTB);
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_blk = (int)__hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_to = 0;
+  }
+  __syncthreads();
+  const int tk = s_blk;
+  if (tk >= nblk) return;
+  const int I = lower ? tk : nblk - 1 - tk;
+  const int r0 = I * kTB;
+  const int bs = min(kTB, n - r0);
+  const int row = tid & (kTB - 1);
+  const int q = tid >> 7;  // column quarter
+  const bool rowok = row < bs;
+  const long long arow = (long long)(r0 + (rowok ? row : 0)) * lda;
+
+  // the diagonal block into LDS, all of a thread's loads in flight at once
+  // (its wait overlaps the first tiles)
+  {
+    constexpr int kD = kTB * kTB / kPT;
+    T v[kD];
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      const int e = tid + kPT * u;
+      const int i = e >> 7, j = e & (kTB - 1);
+      const bool ok = i < bs && j < bs;
+      const TF a = LU[(long long)(r0 + (ok ? i : 0)) * lda + r0 + (ok ? j : 0)];
+      v[u] = ok ? (T)a : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      const int e = tid + kPT * u;
+      Ld[e >> 7][e & (kTB - 1)] = v[u];
+    }
+  }
+  T acc[kRhsChunk];
+#pragma unroll
+  for (int c = 0; c < kRhsChunk; ++c)
+    acc[c] = (q == 0 && rowok && c < cw) ? B[(long long)(r0 + row) * ldb + c0 + c] : T(0);
+
+  // the factors of one tile quarter: row r0 + row, columns cj .. cj + QW
+  auto load_tile = [&](int J, T* f) {
+    const int cj = J * kTB + q * QW;
+    if constexpr (VEC) {
+      constexpr int E = 16 / (int)sizeof(TF);
+      typedef TF vec_t __attribute__((ext_vector_type(E)));
+#pragma unroll
+      for (int u = 0; u < QW / E; ++u) {
+        const bool ok = cj + u * E < n;  // n is a multiple of E on this path
+        const vec_t v = *reinterpret_cast<const vec_t*>(LU + arow + (ok ? cj + u * E : 0));
+#pragma unroll
+        for (int e = 0; e < E; ++e) f[u * E + e] = ok ? (T)v[e] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < QW; ++k) {
+        const bool ok = cj + k < n;
+        const TF v = LU[arow + (ok ? cj + k : 0)];
+        f[k] = ok ? (T)v : T(0);
+      }
+    }
+  };
+  // x_J from its tagged words into xs
+  auto fetch_x = [&](int J) -> bool {
+    const unsigned tag = (unsigned)(J + 1);
+    const unsigned long long* rj = rec + (size_t)J * kTB * kRhsChunk * WPV;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      int bad = 0;
+      for (int e = tid; e < kTB * kRhsChunk; e += kPT) {
+        const int k = e >> 3, c = e & 7;
+        if constexpr (WPV == 1) {
+          const unsigned long long w = xload(&rj[e]);
+          bad |= (unsigned)(w >> 32) != tag;
+          xs[k][c] = __builtin_bit_cast(T, (unsigned)w);
+        } else {
+          const unsigned long long w0 = xload(&rj[2 * e]), w1 = xload(&rj[2 * e + 1]);
+          bad |= ((unsigned)(w0 >> 32) != tag) | ((unsigned)(w1 >> 32) != tag);
+          xs[k][c] = __builtin_bit_cast(
+              T, ((unsigned long long)(unsigned)w1 << 32) | (unsigned long long)(unsigned)w0);
+        }
+      }
+      if (!__syncthreads_or(bad)) return true;
+      if (tid == 0 && __builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) s_to = 1;
+      __syncthreads();
+      if (s_to) return false;
+      __builtin_amdgcn_s_sleep(1);
+    }
+  };
+
+  const int nt = lower ? I : nblk - 1 - I;  // off-diagonal tiles of this block row
+  T f[QW], g[QW];
+  if (nt > 0) load_tile(lower ? 0 : nblk - 1, f);
+  for (int t = 0; t < nt; ++t) {
+    const int J = lower ? t : nblk - 1 - t;
+    if (t + 1 < nt) load_tile(lower ? t + 1 : nblk - 2 - t, g);
+    if (!fetch_x(J)) {
+      if (tid == 0) xstore(&ctl[1], 1u);
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < QW; ++k) {
+#pragma unroll
+      for (int c = 0; c < kRhsChunk; ++c) acc[c] -= f[k] * xs[q * QW + k][c];
+    }
+    __syncthreads();  // xs is rewritten by the next fetch
+#pragma unroll
+    for (int k = 0; k < QW; ++k) f[k] = g[k];
+  }
+  // the column quarters' sums, in a fixed order (deterministic)
+  for (int qq = 1; qq < 4; ++qq) {
+    if (q == qq) {
+#pragma unroll
+      for (int c = 0; c < kRhsChunk; ++c) red[row][c] = acc[c];
+    }
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+      for (int c = 0; c < kRhsChunk; ++c) acc[c] += red[row][c];
+    }
+    __syncthreads();
+  }
+  if (q == 0) {
+#pragma unroll
+    for (int c = 0; c < kRhsChunk; ++c) red[row][c] = acc[c];
+  }
+  __syncthreads();
+
+  // the diagonal block: one wave per right-hand side, lane l holds rows l and
+  // l + 64 (as in trsv_diag_kernel)
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  if (w < cw) {
+    const int i0 = lane, i1 = lane + 64;
+    const int l0 = min(i0, bs - 1), l1 = min(i1, bs - 1);
+    T b0 = red[i0][w], b1 = red[i1][w];
+    auto fwd = [&](int j) {
+      const T a0 = Ld[l0][j], a1 = Ld[l1][j];
+      const T yj = lane_value(j < 64 ? b0 : b1, j & 63);
+      const T n0 = b0 - a0 * yj, n1 = b1 - a1 * yj;
+      b0 = (i0 > j) ? n0 : b0;
+      b1 = (i1 > j) ? n1 : b1;
+    };
+    auto bwd = [&](int j) {
+      const T a0 = Ld[l0][j], a1 = Ld[l1][j], d = Ld[j][j];
+      const T yj = lane_value(j < 64 ? b0 : b1, j & 63) / d;
+      const T n0 = b0 - a0 * yj, n1 = b1 - a1 * yj;
+      b0 = (i0 == j) ? yj : ((i0 < j) ? n0 : b0);
+      b1 = (i1 == j) ? yj : ((i1 < j) ? n1 : b1);
+    };
+    if (lower) {
+      if (bs == kTB) {
+#pragma unroll
+        for (int j = 0; j < kTB; ++j) fwd(j);
+      } else {
+        for (int j = 0; j < bs; ++j) fwd(j);
+      }
+    } else {
+      if (bs == kTB) {
+#pragma unroll
+        for (int j = kTB - 1; j >= 0; --j) bwd(j);
+      } else {
+        for (int j = bs - 1; j >= 0; --j) bwd(j);
+      }
+    }
+    red[i0][w] = b0;
+    red[i1][w] = b1;
+  }
+  __syncthreads();
+  // publish: B (the result) and the tagged words (zeros for missing rows or
+  // right-hand sides, so readers never wait on them)
+  const unsigned tag = (unsigned)(I + 1);
+  unsigned long long* ri = rec + (size_t)I * kTB * kRhsChunk * WPV;
+  for (int e = tid; e < kTB * kRhsChunk; e += kPT) {
+    const int k = e >> 3, c = e & 7;
+    const bool ok = k < bs && c < cw;
+    const T v = ok ? red[k][c] : T(0);
+    if (ok) B[(long long)(r0 + k) * ldb + c0 + c] = v;
+    if constexpr (WPV == 1) {
+      xstore(&ri[e], ((unsigned long long)tag << 32) | __builtin_bit_cast(unsigned, v));
+    } else {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+      xstore(&ri[2 * e], ((unsigned long long)tag << 32) | (b & 0xffffffffull));
+      xstore(&ri[2 * e + 1], ((unsigned long long)tag << 32) | (b >> 32));
+    }
+  }
+}
+
+__global__ void trsv_status_kernel(const unsigned* __restrict__ ctl, int32_t* __restrict__ st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctl[1] != 0u && *st == 0)
+    *st = LP_INFO_BARRIER_TIMEOUT;
+}
+
 // ------------------------------------------------------------- residual
 // One workgroup per row: sum_j |a_ij| and sum_j a_ij x_jc, then
 // |sum - b_ic|; the maxima over rows are combined with 64-bit atomic max on
@@ -376,6 +606,71 @@ int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, cons
   }
   return LP_OK;
 }
+
+// Workspace of the one-launch solves: the tagged words of every block's
+// solution (one pass of up to kRhsChunk right-hand sides) and two control
+// words per pass (ticket, timeout), both triangles.
+size_t lu_solve_workspace_bytes_t(int n, int elem_bytes) {
+  if (n <= 0) return 256;
+  const size_t rec = trsv_rec_words(n, elem_bytes / 4) * sizeof(unsigned long long);
+  return (rec + 255) / 256 * 256 + 256;
+}
+
+template <typename TF, typename T>
+int launch_lu_solve_ws(int n, const TF* LU, long long lda, const int32_t* ipiv,
+                       const int32_t* info, T* B, long long ldb, int nrhs, int32_t* status,
+                       void* work, hipStream_t s) {
+  if (status != nullptr) {
+    hipLaunchKernelGGL(solve_status_kernel, dim3(1), dim3(64), 0, s, info, status);
+    LP_LAUNCH_CHECK();
+  }
+  if (n <= 0 || nrhs <= 0) return LP_OK;
+  hipLaunchKernelGGL((permute_rows_kernel<T>), dim3(1), dim3(1024), 0, s, n, ipiv, B, ldb, nrhs,
+                     info);
+  LP_LAUNCH_CHECK();
+  constexpr int WPV = (int)(sizeof(T) / 4);
+  unsigned long long* rec = reinterpret_cast<unsigned long long*>(work);
+  const size_t rec_words = trsv_rec_words(n, WPV);
+  unsigned* ctl = reinterpret_cast<unsigned*>(
+      reinterpret_cast<char*>(work) + (rec_words * 8 + 255) / 256 * 256);
+  const int nblk = (int)cdiv(n, kTB);
+  // 16-byte factor loads: rows aligned, and no vector straddling column n
+  const bool vec = ((uintptr_t)LU % 16 == 0) && ((lda * (long long)sizeof(TF)) % 16 == 0) &&
+                   (n % (16 / (int)sizeof(TF)) == 0);
+  for (int c0 = 0; c0 < nrhs; c0 += kRhsChunk) {
+    const int cw = min(kRhsChunk, nrhs - c0);
+    for (int tri = 0; tri < 2; ++tri) {
+      int rc = launch_zero_words(rec, rec_words * 2, s);
+      if (rc != LP_OK) return rc;
+      if ((rc = launch_zero_words(ctl, 2, s)) != LP_OK) return rc;
+#define LP_TRSV_P(LOWER, VEC)          \
+      hipLaunchKernelGGL((trsv_persistent_kernel<TF, T, LOWER, VEC>), dim3(nblk), \
+                         dim3(kPT), 0, s, n, LU, lda, B, ldb, c0, cw, rec, ctl, info)
+      if (tri == 0) {
+        if (vec) LP_TRSV_P(true, true); else LP_TRSV_P(true, false);
+      } else {
+        if (vec) LP_TRSV_P(false, true); else LP_TRSV_P(false, false);
+      }
+#undef LP_TRSV_P
+      LP_LAUNCH_CHECK();
+      if (status != nullptr) {
+        hipLaunchKernelGGL(trsv_status_kernel, dim3(1), dim3(64), 0, s, ctl, status);
+        LP_LAUNCH_CHECK();
+      }
+    }
+  }
+  return LP_OK;
+}
+
+template int launch_lu_solve_ws<double, double>(int, const double*, long long, const int32_t*,
+                                                const int32_t*, double*, long long, int, int32_t*,
+                                                void*, hipStream_t);
+template int launch_lu_solve_ws<float, float>(int, const float*, long long, const int32_t*,
+                                              const int32_t*, float*, long long, int, int32_t*,
+                                              void*, hipStream_t);
+template int launch_lu_solve_ws<float, double>(int, const float*, long long, const int32_t*,
+                                               const int32_t*, double*, long long, int, int32_t*,
+                                               void*, hipStream_t);
 
 template int launch_lu_solve<double>(int, const double*, long long, const int32_t*,
                                      const int32_t*, double*, long long, int, int32_t*,

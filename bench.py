@@ -29,7 +29,9 @@ More objects ride on the same line:
     binary64 refinement on A + n I, with the binary64 path timed on that same
     system the same number of times for the speedup);
   * `mixed_ir_unshifted` (the same route on the unshifted headline system:
-    refinement history, fallback, and the time with and without it);
+    refinement history -- classical, then GMRES corrections -- fallback, and
+    the time with and without it), and `mixed_ir_unshifted_fp32` (binary32
+    update operands on that system, where refinement converges);
   * `ptrans` (the paper's matrix transposition kernel C = B + A^T at
     n = 32768: achieved GB/s against the HBM peak, and the paper's n^2
     additions per second);
@@ -219,6 +221,7 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
         "effective_over_fp64_peak": eff / PEAK_FP64_TFLOPS,
         "frac_lowp_peak": eff / PEAK_LOWP_TFLOPS[prec],
         "iterations": last["iterations"], "converged": last["converged"],
+        "gmres_corrections": last["gmres_corrections"], "gmres_steps": last["gmres_steps"],
         "fell_back": last["fell_back"], "scaled_residual": last["scaled_residual"],
         "backward_error_scaled_residual": last["scaled_residual"],
         "history": last["history"],
@@ -604,6 +607,19 @@ def main() -> int:
             log(f"[bench] mixed unshifted done: "
                 f"{line['mixed_ir_unshifted']['ms_per_solve']:.1f} ms/solve, fell back "
                 f"{line['mixed_ir_unshifted']['fell_back']}")
+            # the same unshifted system with binary32 update operands: classical
+            # refinement converges there (kappa u_32 < 1) without the fallback
+            log(f"[bench] mixed fp32 n={mn} unshifted ...")
+            mf = bench_mixed(lp, inputs, torch, dev, mn, mnb, "fp32", 0.0, args.seed,
+                             max(1, R - 1), args.nrhs, fp64_leg=False,
+                             x_ref=(g_head["x"] if g_head is not None else x_head) if same else None,
+                             x_ref_label="oracle" if g_head is not None else "fp64_path")
+            if same:
+                mf["fp64_ms_same_system"] = line["step_times"]["median_ms"]
+                mf["speedup_vs_fp64"] = mf["fp64_ms_same_system"] / mf["ms_per_solve"]
+            line["mixed_ir_unshifted_fp32"] = mf
+            log(f"[bench] mixed fp32 unshifted done: {mf['ms_per_solve']:.1f} ms/solve, fell back "
+                f"{mf['fell_back']}")
         torch.cuda.empty_cache()
     if not args.no_ptrans:
         log(f"[bench] PTRANS n={args.ptrans_n} ...")

@@ -221,7 +221,23 @@ typedef struct {
   double scaled_residual;/* final max_c s_c                                 */
   double history[64];    /* max_c s_c after x0 and after each correction    */
   double t_convert_ms, t_factor_ms, t_solve0_ms, t_refine_ms, t_fallback_ms, t_total_ms;
+  int gmres_corrections; /* corrections computed by GMRES (of `iterations`)  */
+  int gmres_steps;       /* GMRES (Arnoldi) steps over all of them          */
 } lp_ir_report;
+
+/* Refinement options of lu_solve_ir_ex. */
+typedef struct {
+  int max_iter;         /* corrections before giving up (0..62; lu_solve_ir's max_iter) */
+  int gmres;            /* 0: classical corrections only; 1 (default): classical, and
+                           GMRES corrections from the first classical one that does not
+                           cut the scaled residual at least fourfold; 2: GMRES only     */
+  int gmres_restart;    /* Krylov vectors before a restart (1..64; default 64)         */
+  int gmres_max_inner;  /* GMRES steps per correction (default 64); a GMRES correction
+                           that does not halve the scaled residual ends the
+                           refinement (binary64 fallback)                             */
+  double gmres_tol;     /* stop a correction when the preconditioned residual norm has
+                           fallen by this factor (default 1e-10)                        */
+} lp_ir_opts;
 
 /* Bytes of device workspace lu_solve_ir needs. */
 size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs);
@@ -230,7 +246,9 @@ size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs);
  * binary32, factored with the inner update in `prec` (LP_FP32, LP_BF16 or
  * LP_FP16), and x0 solved from those factors; then, repeatedly,
  * r = B - A x (binary64, original A), d = solve(low-precision factors, r),
- * x += d (binary64) until max_c s_c < 16.  Refinement stops as failed after
+ * x += d (binary64) until max_c s_c < 16; from the first correction that does
+ * not cut the residual fourfold, d comes from GMRES preconditioned with the
+ * factors instead (see lu_solve_ir_ex).  Refinement stops as failed after
  * max_iter corrections, when the residual is not finite, or when it grows two
  * steps in a row; the matrix is then factored in binary64 (workspace reused)
  * and solved directly (fell_back = 1).
@@ -241,6 +259,21 @@ size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs);
 int lu_solve_ir(int n, int nb, int prec, const double *A, int lda, const double *B,
                 int ldb, double *X, int ldx, int nrhs, int max_iter, void *work,
                 size_t work_bytes, lp_ir_report *rep, void *stream);
+
+/* lu_solve_ir with options (NULL: max_iter 30 and the defaults above).
+ * GMRES-based refinement (E. Carson and N. J. Higham, SIAM J. Sci. Comput. 39
+ * (2017) and 40 (2018)): the correction equation A d = r is solved by GMRES in
+ * binary64 on U^-1 L^-1 P A d = U^-1 L^-1 P r, with the low-precision factors
+ * (stored in binary32) applied in binary64 arithmetic as the preconditioner;
+ * it converges for conditions kappa(A) well beyond classical refinement's
+ * kappa(A) u_f < 1.  Per GMRES step: one product with A (binary64), one
+ * preconditioner solve, two classical Gram-Schmidt passes with
+ * fixed-order reductions (deterministic), one host synchronization.  The
+ * workspace (lu_solve_ir_workspace_bytes) includes the Krylov basis.  Other
+ * arguments and the fallback as lu_solve_ir; -11 for invalid options. */
+int lu_solve_ir_ex(int n, int nb, int prec, const double *A, int lda, const double *B,
+                   int ldb, double *X, int ldx, int nrhs, const lp_ir_opts *opts, void *work,
+                   size_t work_bytes, lp_ir_report *rep, void *stream);
 
 /* Refinement decision used by lu_solve_ir, from the scaled-residual history
  * h[0..len) (h[0] after x0, h[k] after the k-th correction): returns 1 when the

@@ -37,12 +37,19 @@ class IRReport(ctypes.Structure):
                 ("scaled_residual", ctypes.c_double), ("history", ctypes.c_double * 64),
                 ("t_convert_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
                 ("t_solve0_ms", ctypes.c_double), ("t_refine_ms", ctypes.c_double),
-                ("t_fallback_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("t_fallback_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("gmres_corrections", ctypes.c_int), ("gmres_steps", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}
         d["history"] = [self.history[i] for i in range(self.history_len)]
         return d
+
+
+class IROpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("gmres", ctypes.c_int),
+                ("gmres_restart", ctypes.c_int), ("gmres_max_inner", ctypes.c_int),
+                ("gmres_tol", ctypes.c_double)]
 
 
 class FactorOpts(ctypes.Structure):
@@ -107,6 +114,8 @@ SIGNATURES = {
     "lu_solve_ir_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
     "lu_solve_ir": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ,
                          ctypes.POINTER(IRReport), _VP]),
+    "lu_solve_ir_ex": (_I, [_I, _I, _I, _VP, _I, _VP, _I, _VP, _I, _I, ctypes.POINTER(IROpts),
+                            _VP, _SZ, ctypes.POINTER(IRReport), _VP]),
     "lp_server_create": (_I, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
     "lp_server_destroy": (_I, [_VP]),
     "lp_server_submit": (_I, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64),
@@ -285,8 +294,11 @@ def residual_check(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out=None,
 
 
 def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: int = 30,
-             X=None, work=None, stream=None):
-    """Mixed-precision solve with binary64 iterative refinement. Returns (X, report)."""
+             X=None, work=None, stream=None, gmres: int = 1, gmres_restart: int = 64,
+             gmres_max_inner: int = 64, gmres_tol: float = 1e-10):
+    """Mixed-precision solve with binary64 iterative refinement. Returns (X, report).
+    gmres: 0 classical corrections only, 1 switch to GMRES corrections when
+    classical ones stall (default), 2 GMRES only (lu_solve_ir_ex)."""
     p = _prec(prec)
     lda = _mat(A, torch.float64, "A")
     ldb = _mat(B, torch.float64, "B")
@@ -300,9 +312,11 @@ def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: i
             raise ValueError("unsupported solve_ir arguments")
         work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     rep = IRReport()
-    _check("lu_solve_ir", _lib().lu_solve_ir(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
-                                          X.data_ptr(), ldx, nrhs, max_iter, work.data_ptr(),
-                                          work.numel(), ctypes.byref(rep), _stream(stream)))
+    opts = IROpts(max_iter, gmres, gmres_restart, gmres_max_inner, gmres_tol)
+    _check("lu_solve_ir", _lib().lu_solve_ir_ex(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                                X.data_ptr(), ldx, nrhs, ctypes.byref(opts),
+                                                work.data_ptr(), work.numel(), ctypes.byref(rep),
+                                                _stream(stream)))
     _keep(work, stream)
     return X, rep
 

@@ -121,6 +121,11 @@ int launch_residual(int n, const double* A, long long lda, const double* X, long
 int launch_ptrans(int prec, int n, const void* A, long long lda, const void* B, long long ldb,
                   void* C, long long ldc, hipStream_t s);
 
+// Timing-enabled HIP events from a process-wide pool (per device): an event
+// is handed out again only after it has completed.
+hipError_t acquire_timing_event(hipEvent_t* out);
+void release_timing_event(hipEvent_t e);
+
 // Zero a range of 32-bit words (a kernel, not a memset node).
 int launch_zero_words(void* p, size_t nwords, hipStream_t s);
 

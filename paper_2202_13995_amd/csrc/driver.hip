@@ -229,6 +229,7 @@ StreamPool& stream_pool() {
 // it has completed, so no wait that names it can still be pending.
 class EventPool {
  public:
+  explicit EventPool(unsigned flags) : flags_(flags) {}
   hipError_t get(hipEvent_t* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -242,7 +243,7 @@ class EventPool {
           return hipSuccess;
         }
     }
-    return hipEventCreateWithFlags(out, hipEventDisableTiming);
+    return hipEventCreateWithFlags(out, flags_);
   }
   void put(hipEvent_t ev) {
     int dev = 0;
@@ -256,12 +257,18 @@ class EventPool {
     int dev;
     hipEvent_t e;
   };
+  unsigned flags_;
   std::mutex mu_;
   std::vector<Entry> free_;
 };
 
 EventPool& event_pool() {
-  static EventPool* pool = new EventPool();
+  static EventPool* pool = new EventPool(hipEventDisableTiming);
+  return *pool;
+}
+
+EventPool& timing_event_pool() {
+  static EventPool* pool = new EventPool(hipEventDefault);
   return *pool;
 }
 
@@ -569,6 +576,10 @@ int scratch_address(void** out) {
 }
 
 }  // namespace
+
+hipError_t acquire_timing_event(hipEvent_t* out) { return timing_event_pool().get(out); }
+void release_timing_event(hipEvent_t e) { timing_event_pool().put(e); }
+
 }  // namespace lp
 
 using namespace lp;

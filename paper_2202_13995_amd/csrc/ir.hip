@@ -10,9 +10,14 @@
 //                         benchmark's scaled residual)
 //     d = solve(LU32, r) (binary32 factors and solve)
 //     x = x + d          (binary64)
-// until the scaled residual is below 16.  If it does not get there (too many
-// steps, a non-finite residual, or growth two steps in a row) the matrix is
-// factored in binary64 and solved directly.
+// until the scaled residual is below 16.  When classical refinement stalls
+// (a correction that does not cut the residual at least fourfold) the
+// corrections switch to GMRES-based refinement (Carson & Higham 2017/2018):
+// the correction equation A d = r is solved by GMRES in binary64 on the
+// system left-preconditioned with the low-precision factors, which converges
+// for conditions far beyond classical refinement's kappa u_f < 1.  If neither
+// gets there (too many steps, a non-finite residual, or growth two steps in a
+// row) the matrix is factored in binary64 and solved directly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +51,101 @@ __global__ void add_f32_to_f64_kernel(int rows, int cols, const float* __restric
   }
 }
 
+// ------------------------------------------------------------- GMRES
+// Vectors are contiguous binary64 n-vectors; the Krylov basis V is k rows of
+// n.  Every reduction runs in a fixed order (per-workgroup partial sums, then
+// one workgroup over the partials), so results do not depend on scheduling.
+constexpr int kDotWgs = 256;
+constexpr int kMaxRestart = 64;
+
+// y = A v, one workgroup per row (row-contiguous loads), fixed-order sum
+__global__ __launch_bounds__(256) void matvec_rows_kernel(int n, const double* __restrict__ A,
+                                                          long long lda,
+                                                          const double* __restrict__ v,
+                                                          double* __restrict__ y) {
+  __shared__ double red[4];
+  const double* row = A + (long long)blockIdx.x * lda;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) s += row[j] * v[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) y[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// partial[g][j] = sum over this workgroup's chunk of V[j] . w, j < k
+__global__ __launch_bounds__(256) void dots_partial_kernel(int n, int k,
+                                                           const double* __restrict__ V,
+                                                           const double* __restrict__ w,
+                                                           double* __restrict__ partial) {
+  __shared__ double red[4][kMaxRestart + 2];
+  const int chunk = (int)cdiv(n, gridDim.x);
+  const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V + (long long)j * n;
+    double s = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) s += vj[i] * w[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = s;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += 256)
+    partial[(long long)blockIdx.x * (kMaxRestart + 2) + j] =
+        ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+}
+
+// out[j] = sum over workgroups of partial[g][j], in workgroup order
+__global__ void dots_final_kernel(int k, int groups, const double* __restrict__ partial,
+                                  double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j < k) {
+    double s = 0.0;
+    for (int g = 0; g < groups; ++g) s += partial[(long long)g * (kMaxRestart + 2) + j];
+    out[j] = s;
+  }
+}
+
+// mode 1: w := w - sum_j h[j] V[j]; mode 2: w := w + sum_j h[j] V[j] (j < k)
+__global__ void combine_kernel(int n, int k, const double* __restrict__ V,
+                               const double* __restrict__ h, double* __restrict__ w, int mode) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += h[j] * V[(long long)j * n + i];
+    w[i] = (mode == 1) ? w[i] - acc : w[i] + acc;
+  }
+}
+
+__global__ void scale_kernel(int n, const double* __restrict__ src, double a,
+                             double* __restrict__ dst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i] * a;
+}
+
+// column c of a row-major n x ncols matrix to / from a contiguous vector
+__global__ void get_col_kernel(int n, const double* __restrict__ M, long long ld, int c,
+                               double* __restrict__ v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    v[i] = M[i * ld + c];
+}
+__global__ void add_col_kernel(int n, const double* __restrict__ v, double* __restrict__ M,
+                               long long ld, int c) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    M[i * ld + c] += v[i];
+}
+
+// v := r - v
+__global__ void sub_kernel(int n, const double* __restrict__ r, double* __restrict__ v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    v[i] = r[i] - v[i];
+}
+
 unsigned blocks_for(long long total) {
   long long b = (total + 255) / 256;
   if (b < 1) b = 1;
@@ -56,7 +156,7 @@ unsigned blocks_for(long long total) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct IRLayout {
-  size_t big, fwork, ipiv, info, R, D, out, swork, total;
+  size_t big, fwork, ipiv, info, R, D, out, swork, V, gv, part, hbuf, total;
 };
 
 IRLayout ir_layout(int n, int nb, int prec, int nrhs) {
@@ -80,18 +180,30 @@ IRLayout ir_layout(int n, int nb, int prec, int nrhs) {
   off = align_up(off + sizeof(double) * 5 * (size_t)std::max(nrhs, 1), 256);
   L.swork = off;  // the one-launch triangular solves (binary64 size covers binary32)
   off = align_up(off + lu_solve_workspace_bytes_t(n, 8), 256);
+  // GMRES: the Krylov basis (kMaxRestart + 1 vectors), r and the correction,
+  // the dot-product partials and the small coefficient vectors
+  L.V = off;
+  off = align_up(off + sizeof(double) * (size_t)(kMaxRestart + 1) * n, 256);
+  L.gv = off;
+  off = align_up(off + sizeof(double) * 2 * (size_t)n, 256);
+  L.part = off;
+  off = align_up(off + sizeof(double) * (size_t)kDotWgs * (kMaxRestart + 2), 256);
+  L.hbuf = off;
+  off = align_up(off + sizeof(double) * 4 * (kMaxRestart + 2), 256);
   L.total = off;
   return L;
 }
 
+// Timing events of one call, taken from the library's pool (created once,
+// reused by later calls) and handed back when the call returns.
 struct Events {
   std::vector<hipEvent_t> ev;
   ~Events() {
-    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : ev) release_timing_event(e);
   }
   int record(hipStream_t s, hipEvent_t* out) {
     hipEvent_t e;
-    LP_HIP_TRY(hipEventCreate(&e));
+    LP_HIP_TRY(acquire_timing_event(&e));
     ev.push_back(e);
     LP_HIP_TRY(hipEventRecord(e, s));
     *out = e;
@@ -131,9 +243,16 @@ size_t lu_solve_ir_workspace_bytes(int n, int nb, int prec, int nrhs) {
   return ir_layout(n, nb, prec, nrhs).total;
 }
 
-int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double* B, int ldb,
-                double* X, int ldx, int nrhs, int max_iter, void* work, size_t work_bytes,
-                lp_ir_report* rep, void* stream) {
+int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const double* B, int ldb,
+                   double* X, int ldx, int nrhs, const lp_ir_opts* opts, void* work,
+                   size_t work_bytes, lp_ir_report* rep, void* stream) {
+  lp_ir_opts o;
+  o.max_iter = 30;
+  o.gmres = 1;
+  o.gmres_restart = 64;
+  o.gmres_max_inner = 64;
+  o.gmres_tol = 1e-10;
+  if (opts != nullptr) o = *opts;
   if (n < 0) return -1;
   if (nb < 1) return -2;
   if (prec != LP_FP64 && prec != LP_FP32 && prec != LP_BF16 && prec != LP_FP16) return -3;
@@ -144,7 +263,9 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
   if (X == nullptr && n > 0 && nrhs > 0) return -8;
   if (ldx < std::max(1, nrhs)) return -9;
   if (nrhs < 0) return -10;
-  if (max_iter < 0 || max_iter > 62) return -11;
+  if (o.max_iter < 0 || o.max_iter > 62 || o.gmres < 0 || o.gmres > 2 || o.gmres_restart < 1 ||
+      o.gmres_restart > kMaxRestart || o.gmres_max_inner < 1 || !(o.gmres_tol > 0.0))
+    return -11;
   if (work == nullptr) return -12;
   if (rep == nullptr) return -14;
   const size_t need = lu_solve_ir_workspace_bytes(n, nb, prec, nrhs);
@@ -156,6 +277,7 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
     rep->converged = 1;
     return LP_OK;
   }
+  const int max_iter = o.max_iter;
   const IRLayout L = ir_layout(n, nb, prec, nrhs);
   char* w = (char*)work;
   int32_t* ipiv = (int32_t*)(w + L.ipiv);
@@ -164,6 +286,13 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
   float* D = (float*)(w + L.D);
   double* out_d = (double*)(w + L.out);
   void* swork = w + L.swork;
+  double* Vb = (double*)(w + L.V);
+  double* rv = (double*)(w + L.gv);
+  double* dv = rv + n;
+  double* part = (double*)(w + L.part);
+  double* hd = (double*)(w + L.hbuf);  // [0, kMax+2): first projection; then the second
+  double* hd2 = hd + (kMaxRestart + 2);
+  double* yd = hd + 2 * (kMaxRestart + 2);
   const long long nn = (long long)n;
   Events evs;
   hipEvent_t e0, e_conv = nullptr, e_fact = nullptr, e_solve0 = nullptr, e_ref = nullptr,
@@ -201,18 +330,138 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
                                               swork, s);
   };
 
+  // ---- GMRES on M^-1 A d = M^-1 r (M = the low-precision factors, applied
+  // in binary64), for one right-hand side: r in rv, d out in dv
+  const float* A32 = (const float*)(w + L.big);
+  const unsigned vb = blocks_for(nn);
+  auto precond = [&](double* v) -> int {  // v := M^-1 v
+    return launch_lu_solve_ws<float, double>(n, A32, nn, ipiv, info, v, 1, 1, nullptr, swork, s);
+  };
+  auto dots = [&](const double* V, int k, const double* x, double* out) -> int {
+    hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotWgs), dim3(256), 0, s, n, k, V, x, part);
+    LP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dots_final_kernel, dim3(1), dim3(kMaxRestart + 2), 0, s, k, kDotWgs,
+                       (const double*)part, out);
+    LP_LAUNCH_CHECK();
+    return LP_OK;
+  };
+  auto fetch = [&](const double* src, double* dst, int cnt) -> int {
+    LP_HIP_TRY(hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+    LP_HIP_TRY(hipStreamSynchronize(s));
+    return LP_OK;
+  };
+  auto gmres = [&](int* steps_out) -> int {
+    const int restart = o.gmres_restart;
+    int r = launch_zero_words(dv, 2 * (size_t)n, s);
+    if (r != LP_OK) return r;
+    // z = M^-1 r
+    hipLaunchKernelGGL(scale_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)rv, 1.0, Vb);
+    LP_LAUNCH_CHECK();
+    if ((r = precond(Vb)) != LP_OK) return r;
+    double nz2 = 0.0;
+    if ((r = dots(Vb, 1, Vb, hd)) != LP_OK) return r;
+    if ((r = fetch(hd, &nz2, 1)) != LP_OK) return r;
+    const double beta0 = std::sqrt(nz2);
+    if (!(beta0 > 0.0) || !std::isfinite(beta0)) return LP_OK;
+    int steps = 0;
+    double beta = beta0;
+    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart),
+        g(restart + 1), y(restart), h1(restart + 2), h2(restart + 2);
+    auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * restart + j]; };
+    while (steps < o.gmres_max_inner) {
+      hipLaunchKernelGGL(scale_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)Vb,
+                         1.0 / beta, Vb);
+      LP_LAUNCH_CHECK();
+      const int m = std::min(restart, o.gmres_max_inner - steps);
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;
+      double rel = 1.0;
+      for (int j = 0; j < m; ++j) {
+        double* Vj = Vb + (long long)j * n;
+        double* W = Vb + (long long)(j + 1) * n;
+        hipLaunchKernelGGL(matvec_rows_kernel, dim3(n), dim3(256), 0, s, n, A, (long long)lda,
+                           (const double*)Vj, W);
+        LP_LAUNCH_CHECK();
+        if ((r = precond(W)) != LP_OK) return r;
+        // classical Gram-Schmidt, twice
+        if ((r = dots(Vb, j + 1, W, hd)) != LP_OK) return r;
+        hipLaunchKernelGGL(combine_kernel, dim3(vb), dim3(256), 0, s, n, j + 1, (const double*)Vb,
+                           (const double*)hd, W, 1);
+        LP_LAUNCH_CHECK();
+        if ((r = dots(Vb, j + 2, W, hd2)) != LP_OK) return r;
+        hipLaunchKernelGGL(combine_kernel, dim3(vb), dim3(256), 0, s, n, j + 1, (const double*)Vb,
+                           (const double*)hd2, W, 1);
+        LP_LAUNCH_CHECK();
+        LP_HIP_TRY(hipMemcpyAsync(h1.data(), hd, sizeof(double) * (j + 1), hipMemcpyDeviceToHost,
+                                  s));
+        if ((r = fetch(hd2, h2.data(), j + 2)) != LP_OK) return r;
+        double ww = h2[j + 1];
+        for (int i = 0; i <= j; ++i) {
+          Hm(i, j) = h1[i] + h2[i];
+          ww -= h2[i] * h2[i];
+        }
+        const double hnext = std::sqrt(std::max(ww, 0.0));
+        if (hnext > 0.0) {
+          hipLaunchKernelGGL(scale_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)W,
+                             1.0 / hnext, W);
+          LP_LAUNCH_CHECK();
+        }
+        for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
+          const double t = cs[i] * Hm(i, j) + sn[i] * Hm(i + 1, j);
+          Hm(i + 1, j) = -sn[i] * Hm(i, j) + cs[i] * Hm(i + 1, j);
+          Hm(i, j) = t;
+        }
+        const double den = std::hypot(Hm(j, j), hnext);
+        cs[j] = Hm(j, j) / den;
+        sn[j] = hnext / den;
+        Hm(j, j) = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        ++steps;
+        rel = std::fabs(g[j + 1]) / beta0;
+        if (!std::isfinite(rel) || rel <= o.gmres_tol || hnext == 0.0) break;
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < k; ++l) t -= Hm(i, l) * y[l];
+        y[i] = t / Hm(i, i);
+      }
+      LP_HIP_TRY(hipMemcpyAsync(yd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(combine_kernel, dim3(vb), dim3(256), 0, s, n, k, (const double*)Vb,
+                         (const double*)yd, dv, 2);
+      LP_LAUNCH_CHECK();
+      if (!(rel > o.gmres_tol) || !std::isfinite(rel) || steps >= o.gmres_max_inner) break;
+      // restart: z = M^-1 (r - A d)
+      hipLaunchKernelGGL(matvec_rows_kernel, dim3(n), dim3(256), 0, s, n, A, (long long)lda,
+                         (const double*)dv, Vb);
+      LP_LAUNCH_CHECK();
+      hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)rv, Vb);
+      LP_LAUNCH_CHECK();
+      if ((r = precond(Vb)) != LP_OK) return r;
+      if ((r = dots(Vb, 1, Vb, hd)) != LP_OK) return r;
+      if ((r = fetch(hd, &nz2, 1)) != LP_OK) return r;
+      beta = std::sqrt(nz2);
+      if (!(beta > 0.0)) break;
+    }
+    *steps_out += steps;
+    return LP_OK;
+  };
+
   bool need_fallback = (prec == LP_FP64);
   if (prec != LP_FP64) {
     // low-precision factorization and the first solve
-    float* A32 = (float*)(w + L.big);
-    if ((rc = launch_convert(1, n, n, A, lda, A32, nn, s)) != LP_OK) return rc;
+    float* A32w = (float*)(w + L.big);
+    if ((rc = launch_convert(1, n, n, A, lda, A32w, nn, s)) != LP_OK) return rc;
     if ((rc = evs.record(s, &e_conv)) != LP_OK) return rc;
-    if ((rc = lu_factor(n, nb, prec, A32, n, ipiv, info, w + L.fwork,
+    if ((rc = lu_factor(n, nb, prec, A32w, n, ipiv, info, w + L.fwork,
                         lu_workspace_bytes(n, nb, prec), s)) != LP_OK)
       return rc;
     if ((rc = evs.record(s, &e_fact)) != LP_OK) return rc;
     if ((rc = launch_convert(1, n, nrhs, B, ldb, D, nrhs, s)) != LP_OK) return rc;
-    if ((rc = launch_lu_solve_ws<float, float>(n, A32, nn, ipiv, info, D, nrhs, nrhs, nullptr,
+    if ((rc = launch_lu_solve_ws<float, float>(n, A32w, nn, ipiv, info, D, nrhs, nrhs, nullptr,
                                                 swork, s)) != LP_OK)
       return rc;
     if ((rc = launch_convert(0, n, nrhs, D, nrhs, X, ldx, s)) != LP_OK) return rc;
@@ -226,6 +475,7 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
     if (info_h != 0) {
       need_fallback = true;
     } else {
+      bool use_gmres = (o.gmres == 2);
       for (;;) {
         const int d = lp_ir_decide(rep->history, rep->history_len, rep->iterations, max_iter);
         if (d == 1) break;
@@ -233,17 +483,43 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
           need_fallback = true;
           break;
         }
-        // d = solve(LU32, r); x += d
-        if ((rc = launch_convert(1, n, nrhs, R, nrhs, D, nrhs, s)) != LP_OK) return rc;
-        if ((rc = launch_lu_solve_ws<float, float>(n, A32, nn, ipiv, info, D, nrhs, nrhs,
-                                                    nullptr, swork, s)) != LP_OK)
-          return rc;
-        hipLaunchKernelGGL(add_f32_to_f64_kernel, dim3(blocks_for(nn * nrhs)), dim3(256), 0, s,
-                           n, nrhs, D, (long long)nrhs, X, (long long)ldx);
-        LP_LAUNCH_CHECK();
+        if (!use_gmres) {
+          // classical correction: d = solve(LU32, r); x += d
+          if ((rc = launch_convert(1, n, nrhs, R, nrhs, D, nrhs, s)) != LP_OK) return rc;
+          if ((rc = launch_lu_solve_ws<float, float>(n, A32w, nn, ipiv, info, D, nrhs, nrhs,
+                                                      nullptr, swork, s)) != LP_OK)
+            return rc;
+          hipLaunchKernelGGL(add_f32_to_f64_kernel, dim3(blocks_for(nn * nrhs)), dim3(256), 0, s,
+                             n, nrhs, D, (long long)nrhs, X, (long long)ldx);
+          LP_LAUNCH_CHECK();
+        } else {
+          // GMRES correction per right-hand side
+          for (int c = 0; c < nrhs; ++c) {
+            hipLaunchKernelGGL(get_col_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)R,
+                               (long long)nrhs, c, rv);
+            LP_LAUNCH_CHECK();
+            if ((rc = gmres(&rep->gmres_steps)) != LP_OK) return rc;
+            hipLaunchKernelGGL(add_col_kernel, dim3(vb), dim3(256), 0, s, n, (const double*)dv, X,
+                               (long long)ldx, c);
+            LP_LAUNCH_CHECK();
+          }
+          rep->gmres_corrections++;
+        }
         rep->iterations++;
         if ((rc = scaled_residual(&sres)) != LP_OK) return rc;
         rep->history[rep->history_len++] = sres;
+        // a classical correction that does not cut the residual fourfold:
+        // the factors are too far from A for it, switch to GMRES; a GMRES
+        // correction that does not halve it: give up (binary64 fallback)
+        const int len = rep->history_len;
+        const double last = rep->history[len - 1], prev = rep->history[len - 2];
+        if (!(last < 16.0)) {
+          if (use_gmres && !(last <= 0.5 * prev)) {
+            need_fallback = true;
+            break;
+          }
+          if (!use_gmres && o.gmres == 1 && !(last <= 0.25 * prev)) use_gmres = true;
+        }
         if (rep->history_len >= 64) {
           need_fallback = lp_ir_decide(rep->history, rep->history_len, rep->iterations,
                                        max_iter) != 1;
@@ -279,6 +555,20 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
   rep->t_fallback_ms = ms_between(e_fb0, e_end);
   rep->t_total_ms = ms_between(e0, e_end);
   return LP_OK;
+}
+
+int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double* B, int ldb,
+                double* X, int ldx, int nrhs, int max_iter, void* work, size_t work_bytes,
+                lp_ir_report* rep, void* stream) {
+  lp_ir_opts o;
+  o.max_iter = max_iter;
+  o.gmres = 1;
+  o.gmres_restart = 64;
+  o.gmres_max_inner = 64;
+  o.gmres_tol = 1e-10;
+  if (max_iter < 0 || max_iter > 62) return -11;
+  return lu_solve_ir_ex(n, nb, prec, A, lda, B, ldb, X, ldx, nrhs, &o, work, work_bytes, rep,
+                        stream);
 }
 
 }  // extern "C"

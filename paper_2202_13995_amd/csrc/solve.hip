@@ -66,6 +66,73 @@ __global__ __launch_bounds__(1024) void permute_rows_kernel(int n, const int32_t
   }
 }
 
+// The same B := P B in two launches: the net permutation of every chunk of
+// 1024 interchanges is built at once (one workgroup per chunk: a chunk's plan
+// depends only on its own entries of ipiv), then one workgroup applies the
+// chunks' gathers to B in order.  Plans: per chunk one count and up to 2048
+// (destination, source) row pairs.
+constexpr int kPlanChunk = 1024;
+constexpr int kPlanInts = 1 + 4 * kPlanChunk;
+
+__global__ __launch_bounds__(1024) void solve_plans_kernel(int n, const int32_t* __restrict__ ipiv,
+                                                           int* __restrict__ plans,
+                                                           const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  __shared__ int piv[kPlanChunk];
+  __shared__ int nxt[kPlanChunk];
+  __shared__ int Bv[kPlanChunk];
+  __shared__ int flag[2 * kPlanChunk];
+  __shared__ int dst[2 * kPlanChunk];
+  __shared__ int src[2 * kPlanChunk];
+  __shared__ int nent;
+  const int k1 = blockIdx.x * kPlanChunk;
+  const int k2 = min(n, k1 + kPlanChunk);
+  if ((int)threadIdx.x < k2 - k1) piv[threadIdx.x] = ipiv[k1 + threadIdx.x];
+  __syncthreads();
+  build_swap_plan(piv, k1, k2, nxt, Bv, nullptr, flag, dst, src, &nent);
+  __syncthreads();
+  int* out = plans + (size_t)blockIdx.x * kPlanInts;
+  const int ne = nent;
+  if (threadIdx.x == 0) out[0] = ne;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    out[1 + e] = dst[e];
+    out[1 + 2 * kPlanChunk + e] = src[e];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void apply_plans_kernel(int nchunks, const int* __restrict__ plans,
+                                                           T* __restrict__ B, long long ldb,
+                                                           int nrhs,
+                                                           const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  constexpr int Q = 16;  // 2048 entries x 8 columns / 1024 threads
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int* pl = plans + (size_t)ch * kPlanInts;
+    const int ne = pl[0];
+    for (int c0 = 0; c0 < nrhs; c0 += kRhsChunk) {
+      const int cw = min(kRhsChunk, nrhs - c0);
+      T v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + 1024 * q;
+        const int ent = e >> 3;
+        const int col = e & 7;
+        if (ent < ne && col < cw) v[q] = B[(long long)pl[1 + 2 * kPlanChunk + ent] * ldb + c0 + col];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + 1024 * q;
+        const int ent = e >> 3;
+        const int col = e & 7;
+        if (ent < ne && col < cw) B[(long long)pl[1 + ent] * ldb + c0 + col] = v[q];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------- diagonal-block solves
 // lower == true: unit lower forward substitution on rows [r0, r0 + bs).
 // lower == false: upper back substitution (divides by the diagonal).
@@ -610,10 +677,12 @@ int launch_lu_solve(int n, const T* LU, long long lda, const int32_t* ipiv, cons
 // Workspace of the one-launch solves: the tagged words of every block's
 // solution (one pass of up to kRhsChunk right-hand sides) and two control
 // words per pass (ticket, timeout), both triangles.
+size_t plans_bytes(int n) { return sizeof(int) * (size_t)kPlanInts * (size_t)cdiv(n, kPlanChunk); }
+
 size_t lu_solve_workspace_bytes_t(int n, int elem_bytes) {
   if (n <= 0) return 256;
   const size_t rec = trsv_rec_words(n, elem_bytes / 4) * sizeof(unsigned long long);
-  return (rec + 255) / 256 * 256 + 256;
+  return (rec + 255) / 256 * 256 + 256 + (plans_bytes(n) + 255) / 256 * 256;
 }
 
 template <typename TF, typename T>
@@ -625,14 +694,18 @@ int launch_lu_solve_ws(int n, const TF* LU, long long lda, const int32_t* ipiv,
     LP_LAUNCH_CHECK();
   }
   if (n <= 0 || nrhs <= 0) return LP_OK;
-  hipLaunchKernelGGL((permute_rows_kernel<T>), dim3(1), dim3(1024), 0, s, n, ipiv, B, ldb, nrhs,
-                     info);
-  LP_LAUNCH_CHECK();
   constexpr int WPV = (int)(sizeof(T) / 4);
   unsigned long long* rec = reinterpret_cast<unsigned long long*>(work);
   const size_t rec_words = trsv_rec_words(n, WPV);
   unsigned* ctl = reinterpret_cast<unsigned*>(
       reinterpret_cast<char*>(work) + (rec_words * 8 + 255) / 256 * 256);
+  int* plans = reinterpret_cast<int*>(reinterpret_cast<char*>(ctl) + 256);
+  const int nchunks = (int)cdiv(n, kPlanChunk);
+  hipLaunchKernelGGL(solve_plans_kernel, dim3(nchunks), dim3(1024), 0, s, n, ipiv, plans, info);
+  LP_LAUNCH_CHECK();
+  hipLaunchKernelGGL((apply_plans_kernel<T>), dim3(1), dim3(1024), 0, s, nchunks,
+                     (const int*)plans, B, ldb, nrhs, info);
+  LP_LAUNCH_CHECK();
   const int nblk = (int)cdiv(n, kTB);
   // 16-byte factor loads: rows aligned, and no vector straddling column n
   const bool vec = ((uintptr_t)LU % 16 == 0) && ((lda * (long long)sizeof(TF)) % 16 == 0) &&

@@ -40,6 +40,8 @@ def main(argv=None) -> int:
     ap.add_argument("--reps", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2202)
     ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--gmres", type=int, default=1,
+                    help="mixed: 0 classical refinement only, 1 GMRES when it stalls, 2 GMRES")
     args = ap.parse_args(argv)
 
     import torch
@@ -91,8 +93,13 @@ def main(argv=None) -> int:
         work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         for r in range(args.reps):
             t0 = time.perf_counter()
-            _, rep = lp.solve_ir(A0, B0, nb, prec, X=X, work=work)
-            say(f"rep {r}: {1e3 * (time.perf_counter() - t0):.1f} ms {rep.as_dict()['history']}")
+            _, rep = lp.solve_ir(A0, B0, nb, prec, X=X, work=work, gmres=args.gmres)
+            d = rep.as_dict()
+            say(f"rep {r}: {1e3 * (time.perf_counter() - t0):.1f} ms, {d['iterations']} "
+                f"corrections ({d['gmres_corrections']} GMRES, {d['gmres_steps']} steps), "
+                f"fell back {d['fell_back']}, history {d['history']}, phases "
+                f"factor {d['t_factor_ms']:.0f} refine {d['t_refine_ms']:.0f} "
+                f"fallback {d['t_fallback_ms']:.0f} ms")
         return 0
 
     if args.what == "solve":

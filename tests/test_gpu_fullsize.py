@@ -214,9 +214,11 @@ def test_mixed_bf16_n65536(lp, shift):
         assert r["fell_back"] == 0 and r["iterations"] <= 6, r
         assert h[-1] < 16 and len(h) == r["iterations"] + 1
     elif r["fell_back"]:
-        # the refinement gave up by its own rule (the residual history is what
-        # the decision function calls a failure), and the binary64 route solved it
-        assert lp.ir_decide(h, r["iterations"], 30) == 2, r
+        # the refinement gave up by its own rules -- the history is what the
+        # decision function calls a failure, or a GMRES correction did not halve
+        # the scaled residual -- and the binary64 route solved it
+        gmres_gave_up = r["gmres_corrections"] > 0 and not (h[-1] <= 0.5 * h[-2])
+        assert lp.ir_decide(h, r["iterations"], 30) == 2 or gmres_gave_up, r
         assert r["fallback_info"] == 0
     else:
         assert h[-1] < 16 and lp.ir_decide(h, r["iterations"], 30) == 1, r

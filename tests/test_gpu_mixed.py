@@ -188,3 +188,68 @@ def test_fp64_through_refinement_entry(lp):
     assert r["converged"] == 1 and r["fell_back"] == 0 and r["iterations"] == 0
     x_o = oracle.solve(A, B)
     assert np.max(np.abs(host(X) - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+
+
+# ------------------------------------------------------------------ GMRES-IR
+@pytest.mark.parametrize("n,nb,nrhs", [(2048, 256, 1), (1500, 128, 3)])
+def test_gmres_refinement_unshifted(lp, n, nb, nrhs):
+    """GMRES corrections only (gmres=2) on an unshifted matrix with bfloat16
+    factors: converges without the binary64 fallback; x against the oracle."""
+    A = inputs.matrix(81 + n, n)
+    B = inputs.rhs(81 + n, n, nrhs)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, "bf16", gmres=2, gmres_max_inner=200)
+    r = rep.as_dict()
+    print(f"GMRES-IR n={n}: {r['iterations']} corrections, {r['gmres_steps']} GMRES steps, "
+          f"history {r['history']}")
+    assert r["converged"] == 1 and r["fell_back"] == 0, r
+    assert r["gmres_corrections"] == r["iterations"] >= 1 and r["gmres_steps"] >= 1
+    x_o = oracle.solve(A, B)
+    x = host(X)
+    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+    assert np.all(oracle.residual(A, x, B)[:, 0] < 16)
+
+
+def test_gmres_switch_after_classical_stall(lp):
+    """Default mode: classical corrections until one fails to cut the residual
+    fourfold, then GMRES; the switch is visible in the history."""
+    n, nb = 4096, 256
+    A = inputs.matrix(5, n)
+    B = inputs.rhs(5, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, "bf16", gmres_max_inner=200)
+    r = rep.as_dict()
+    h = r["history"]
+    print(f"n={n} default refinement: history {h}, gmres corrections {r['gmres_corrections']}")
+    assert r["converged"] == 1 and r["fell_back"] == 0, r
+    ncl = r["iterations"] - r["gmres_corrections"]
+    # every classical correction but the last cut the residual fourfold
+    for i in range(1, ncl):
+        assert h[i] <= 0.25 * h[i - 1]
+    if r["gmres_corrections"]:
+        assert not (h[ncl] <= 0.25 * h[ncl - 1]) if ncl >= 1 else True
+    # stopping at s < 16 bounds the forward error by about kappa * s * n * u
+    x_o = oracle.solve(A, B)
+    kappa = np.linalg.cond(A, np.inf)
+    err = np.max(np.abs(host(X) - x_o)) / np.max(np.abs(x_o))
+    print(f"forward error {err:.2e}, kappa_inf {kappa:.2e}")
+    assert err <= 4 * kappa * max(r["scaled_residual"], 1.0) * n * 2.0 ** -53
+
+
+def test_gmres_refinement_is_deterministic(lp):
+    n, nb = 1200, 128
+    A = inputs.matrix(17, n)
+    B = inputs.rhs(17, n, 2)
+    xs = []
+    for _ in range(2):
+        X, rep = lp.solve_ir(cuda(A), cuda(B), nb, "bf16", gmres=2, gmres_max_inner=200)
+        xs.append(host(X))
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_classical_only_mode(lp):
+    n, nb = 1000, 64
+    A = inputs.matrix(77, n)
+    B = inputs.rhs(77, n, 1)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, "bf16", gmres=0)
+    r = rep.as_dict()
+    assert r["gmres_corrections"] == 0 and r["gmres_steps"] == 0
+    assert r["scaled_residual"] < 16

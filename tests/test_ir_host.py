@@ -77,3 +77,57 @@ def test_reference_refinement_unshifted_fp32():
     assert ok
     x_o = oracle.solve(a, b)
     assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
+
+
+# ----------------------------------------------------------------- GMRES-IR
+def test_gmres_finite_termination_matches_library_solve():
+    # without a preconditioner and with restart >= n, GMRES reaches the exact
+    # solution in at most n steps (up to rounding): pins Arnoldi, the Givens
+    # rotations and the back substitution against a library solve
+    from oracle import ir
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 5, 17, 40):
+        a = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(1, 2, n))
+        r = rng.uniform(-1, 1, n)
+        d, steps, rel = ir.gmres(lambda v: a @ v, lambda v: v, r, restart=n, tol=1e-14, max_it=n)
+        assert steps <= n
+        assert np.max(np.abs(d - np.linalg.solve(a, r))) <= 1e-10 * np.max(np.abs(d))
+
+
+def test_gmres_exact_preconditioner_one_step():
+    from oracle import ir
+    rng = np.random.default_rng(5)
+    n = 30
+    a = rng.uniform(-1, 1, (n, n)) + 3 * np.eye(n)
+    r = rng.uniform(-1, 1, n)
+    d, steps, rel = ir.gmres(lambda v: a @ v, lambda v: np.linalg.solve(a, v), r, restart=10,
+                             tol=1e-12, max_it=10)
+    assert steps == 1 and rel <= 1e-12
+    assert np.max(np.abs(a @ d - r)) <= 1e-12 * np.max(np.abs(r))
+
+
+def test_gmres_restarts_still_converge():
+    from oracle import ir
+    rng = np.random.default_rng(6)
+    n = 60
+    a = rng.uniform(-1, 1, (n, n)) + 8 * np.eye(n)
+    r = rng.uniform(-1, 1, n)
+    d, steps, rel = ir.gmres(lambda v: a @ v, lambda v: v, r, restart=5, tol=1e-11, max_it=400)
+    assert rel <= 1e-11 and steps > 5
+    assert np.max(np.abs(d - np.linalg.solve(a, r))) <= 1e-9
+
+
+def test_gmres_ir_needs_fewer_corrections_than_classical():
+    # unshifted uniform matrix with bfloat16 factors: classical refinement
+    # needs several corrections, GMRES-IR one (Carson & Higham)
+    import inputs
+    import oracle
+    from oracle import ir
+    n = 1024
+    a = inputs.matrix(77, n)
+    b = inputs.rhs(77, n, 1)[:, 0]
+    x_c, h_c, conv_c, k_c = ir.refine(a, b, "bf16")
+    x_g, h_g, conv_g, k_g, inner = ir.gmres_ir(a, b, "bf16")
+    assert conv_g and k_g == 1 and k_c >= 4
+    x_o = oracle.solve(a, b)
+    assert np.max(np.abs(x_g - x_o)) / np.max(np.abs(x_o)) <= 1e-9

@@ -35,8 +35,9 @@ More objects ride on the same line:
   * `ptrans` (the paper's matrix transposition kernel C = B + A^T at
     n = 32768: achieved GB/s against the HBM peak, and the paper's n^2
     additions per second);
-  * `serving` (an open-loop Poisson stream through the continuous-batching
-    server: p50/p99 latency overall and per request class, aggregate TFLOP/s).
+  * `serving` (the continuous-batching server: saturation measured with a
+    burst, then open-loop Poisson streams at 25/50/80% of it, 2000 requests
+    each: p50/p99 latency overall and per request class, aggregate TFLOP/s).
 One process, one GPU; prints one JSON line on stdout, progress on stderr.
 """
 from __future__ import annotations
@@ -316,21 +317,16 @@ def bench_ptrans(lp, inputs, torch, dev, n, seed, reps):
     return out
 
 
-def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small_n_max=512,
-                  large_slots=8):
-    """Open-loop Poisson stream of solves through the continuous-batching server.
-
-    Sizes are log-uniform in [64, 4096], 1-8 right-hand sides, half binary64 and
-    half the low-precision route; A uniform[-0.5,0.5).  Inputs are generated on
-    the device before the clock starts; a request is submitted when its arrival
-    time has passed, and its latency runs from its arrival time to the poll that
-    returns it."""
+def serving_requests(inputs, torch, dev, nreq, seed, lowp):
+    """The request set of the serving measurements: n = round(exp(U(ln 64,
+    ln 4096))), 1-8 right-hand sides, half binary64 and half the low-precision
+    route, A and B uniform[-0.5,0.5) with seed + 1 + request index, generated
+    on the device before any clock starts."""
     import numpy as np
     rng = np.random.default_rng(seed)
     ns = np.exp(rng.uniform(np.log(64), np.log(4096), nreq)).astype(int)
     nrhs = rng.integers(1, 9, nreq)
     precs = np.where(rng.random(nreq) < 0.5, "fp64", lowp)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
     reqs = []
     for i in range(nreq):
         n, r = int(ns[i]), int(nrhs[i])
@@ -340,60 +336,63 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small
         inputs.fill_rhs_(B, seed + 1 + i)
         reqs.append((A, B, torch.empty_like(B), n, r, str(precs[i])))
     torch.cuda.synchronize()
+    return reqs
+
+
+def serve_stream(lp, torch, sv, reqs, arrivals):
+    """One open-loop stream: request i is submitted once arrivals[i] (seconds)
+    has passed, whatever is still running (no coordinated omission); its
+    latency runs from its arrival time to the poll that returns it."""
+    import numpy as np
 
     def nb_for(n):
         return 64 if n <= 1024 else 128
 
-    with lp.Server(memory_bytes=int(mem_gib * 2**30), small_n_max=small_n_max, max_batch=256,
-                   batch_slots=4, large_slots=large_slots) as sv:
-        # warm-up: one request of each route, untimed
-        for (n, pr) in ((100, "fp64"), (100, lowp), (1500, "fp64"), (1500, lowp)):
-            A = torch.empty((n, n), dtype=torch.float64, device=dev)
-            inputs.fill_matrix_(A, 1)
-            B = torch.empty((n, 1), dtype=torch.float64, device=dev)
-            inputs.fill_rhs_(B, 1)
-            sv.submit(A, B, torch.empty_like(B), prec=pr, nb=nb_for(n))
-        sv.drain()
-        torch.cuda.synchronize()
-        t_arr = {}
-        t_done = {}
-        res = {}
-        i = 0
-        t0 = time.perf_counter()
-        while len(t_done) < nreq:
-            now = time.perf_counter() - t0
-            while i < nreq and arrivals[i] <= now:
-                A, B, X, n, r, pr = reqs[i]
-                t = sv.submit(A, B, X, prec=pr, nb=nb_for(n))
-                t_arr[t] = (i, arrivals[i])
-                i += 1
-            got = sv.poll()
-            now = time.perf_counter() - t0
-            for d in got:
-                t_done[d["ticket"]] = now
-                res[d["ticket"]] = d
-            if not got and i < nreq and arrivals[i] > now + 2e-4:
-                time.sleep(1e-4)
-        t_end = time.perf_counter() - t0
+    nreq = len(reqs)
+    t_arr, t_done, res = {}, {}, {}
+    i = 0
+    t0 = time.perf_counter()
+    while len(t_done) < nreq:
+        now = time.perf_counter() - t0
+        while i < nreq and arrivals[i] <= now:
+            A, B, X, n, r, pr = reqs[i]
+            t = sv.submit(A, B, X, prec=pr, nb=nb_for(n))
+            t_arr[t] = (i, arrivals[i])
+            i += 1
+        got = sv.poll()
+        now = time.perf_counter() - t0
+        for d in got:
+            t_done[d["ticket"]] = now
+            res[d["ticket"]] = d
+        if not got and i < nreq and arrivals[i] > now + 2e-4:
+            time.sleep(1e-4)
+    t_end = time.perf_counter() - t0
     lat = np.array([1e3 * (t_done[t] - t_arr[t][1]) for t in t_done])
     classes = {}
     for t in t_done:
-        i = t_arr[t][0]
-        n_i, pr_i = reqs[i][3], reqs[i][5]
-        key = ("batched" if res[t]["batched"] else "blocked") + "/" + pr_i + \
-              ("/n<1024" if n_i < 1024 else "/n>=1024")
+        k = t_arr[t][0]
+        n_k, pr_k = reqs[k][3], reqs[k][5]
+        key = ("batched" if res[t]["batched"] else "blocked") + "/" + pr_k + \
+              ("/n<1024" if n_k < 1024 else "/n>=1024")
         classes.setdefault(key, []).append(1e3 * (t_done[t] - t_arr[t][1]))
+    dev_ms = {}
+    for t in t_done:
+        k = t_arr[t][0]
+        key = ("batched" if res[t]["batched"] else "blocked") + "/" + reqs[k][5] + \
+              ("/n<1024" if reqs[k][3] < 1024 else "/n>=1024")
+        dev_ms.setdefault(key, []).append(res[t]["device_ms"])
+    # latency = the request's own device time + the time it waited (admission,
+    # a free workgroup or slot, the device shared with other requests)
     by_class = {k: {"count": len(v), "p50_ms": float(np.percentile(v, 50)),
-                    "p99_ms": float(np.percentile(v, 99))} for k, v in sorted(classes.items())}
+                    "p99_ms": float(np.percentile(v, 99)),
+                    "device_p50_ms": float(np.percentile(dev_ms[k], 50)),
+                    "device_p99_ms": float(np.percentile(dev_ms[k], 99))}
+                for k, v in sorted(classes.items())}
     total = sum(flops(q[3], q[4]) for q in reqs)
     span = t_end - float(arrivals[0])
     bad = [d for d in res.values() if d["status"] != 0 or not d["scaled_residual"] < 16.0]
     return {
-        "workload": f"Poisson stream, {nreq} requests at {rate:g}/s offered, n log-uniform "
-                    f"[64,4096], 1-8 rhs, half fp64 / half {lowp}+binary64 refinement, "
-                    f"A uniform[-0.5,0.5), n<={small_n_max} batched, {large_slots} blocked-path "
-                    f"slots, pool {mem_gib:g} GiB",
-        "requests": nreq, "offered_rate_per_s": rate,
+        "requests": nreq,
         "achieved_rate_per_s": nreq / span,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
@@ -403,6 +402,52 @@ def bench_serving(lp, inputs, torch, dev, nreq, rate, seed, mem_gib, lowp, small
         "by_class": by_class,
         "fell_back": int(sum(d["fell_back"] for d in res.values())),
         "failed": len(bad),
+    }
+
+
+def bench_serving(lp, inputs, torch, dev, nreq, seed, mem_gib, lowp, small_n_max, large_slots,
+                  fractions, burst):
+    """Continuous-batching server under open-loop Poisson load.  Saturation is
+    measured first with a burst (every request submitted at t = 0: requests per
+    second = count / makespan); then arrival rates at the given fractions of
+    it, each over the same `nreq` requests."""
+    import numpy as np
+    reqs = serving_requests(inputs, torch, dev, nreq, seed, lowp)
+    with lp.Server(memory_bytes=int(mem_gib * 2**30), small_n_max=small_n_max, max_batch=256,
+                   large_slots=large_slots) as sv:
+        # warm-up: one request of each route, untimed
+        for (n, pr) in ((100, "fp64"), (100, lowp), (1500, "fp64"), (1500, lowp)):
+            A = torch.empty((n, n), dtype=torch.float64, device=dev)
+            inputs.fill_matrix_(A, 1)
+            B = torch.empty((n, 1), dtype=torch.float64, device=dev)
+            inputs.fill_rhs_(B, 1)
+            sv.submit(A, B, torch.empty_like(B), prec=pr, nb=64 if n <= 1024 else 128)
+        sv.drain()
+        torch.cuda.synchronize()
+        nb_ = min(burst, nreq)
+        sat = serve_stream(lp, torch, sv, reqs[:nb_], np.zeros(nb_))
+        rate_sat = sat["achieved_rate_per_s"]
+        log(f"[bench] serving burst of {nb_}: {rate_sat:.1f} requests/s, p50 {sat['p50_ms']:.1f} ms")
+        sweep = []
+        rng = np.random.default_rng(seed + 7)
+        for f in fractions:
+            rate = f * rate_sat
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+            r = serve_stream(lp, torch, sv, reqs, arrivals)
+            r.update({"fraction_of_saturation": f, "offered_rate_per_s": rate})
+            sweep.append(r)
+            log(f"[bench] serving at {f:.2f} of saturation ({rate:.1f}/s): p50 {r['p50_ms']:.2f} ms, "
+                f"p99 {r['p99_ms']:.2f} ms")
+    top = sweep[-1] if sweep else sat
+    return {
+        "workload": f"Poisson streams of {nreq} requests, n log-uniform [64,4096], 1-8 rhs, half "
+                    f"fp64 / half {lowp}+binary64 refinement, A uniform[-0.5,0.5), n<={small_n_max} "
+                    f"in the persistent batched kernel, {large_slots} blocked-path slots, pool "
+                    f"{mem_gib:g} GiB; arrival rates at {fractions} of the burst-measured saturation",
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+        "aggregate_tflops": top["aggregate_tflops"],
+        "saturation": dict(sat, burst_requests=nb_),
+        "sweep": sweep,
     }
 
 
@@ -434,13 +479,16 @@ def main() -> int:
                     help="order of the system compared with the oracle's stored solution")
     ap.add_argument("--parity-nb", type=int, default=256)
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-rate", type=float, default=100.0,
-                    help="offered requests per second (about 3/4 of the measured saturation)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per arrival rate")
+    ap.add_argument("--serve-fractions", default="0.25,0.5,0.8",
+                    help="arrival rates as fractions of the measured saturation")
+    ap.add_argument("--serve-burst", type=int, default=1000,
+                    help="requests of the burst that measures saturation")
     ap.add_argument("--serve-gib", type=float, default=16.0)
     ap.add_argument("--serve-lowp", default="fp32", choices=["bf16", "fp16", "fp32"])
-    ap.add_argument("--serve-small-n", type=int, default=512,
-                    help="requests up to this n run in the batched launch")
+    ap.add_argument("--serve-small-n", type=int, default=128,
+                    help="requests up to this n run in the persistent batched kernel")
     ap.add_argument("--serve-large-slots", type=int, default=8)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -626,13 +674,13 @@ def main() -> int:
         line["ptrans"] = bench_ptrans(lp, inputs, torch, dev, args.ptrans_n, args.seed, 20)
         log(f"[bench] PTRANS done: {line['ptrans']['fp64']['GBps']:.0f} GB/s (binary64)")
     if not args.no_serve:
-        log(f"[bench] serving {args.serve_requests} requests at {args.serve_rate:g}/s ...")
-        line["serving"] = bench_serving(lp, inputs, torch, dev, args.serve_requests,
-                                        args.serve_rate, args.seed, args.serve_gib,
-                                        args.serve_lowp, args.serve_small_n,
-                                        args.serve_large_slots)
+        fr = [float(v) for v in args.serve_fractions.split(",") if v]
+        log(f"[bench] serving: {args.serve_requests} requests per rate ...")
+        line["serving"] = bench_serving(lp, inputs, torch, dev, args.serve_requests, args.seed,
+                                        args.serve_gib, args.serve_lowp, args.serve_small_n,
+                                        args.serve_large_slots, fr, args.serve_burst)
         log(f"[bench] serving done: p50 {line['serving']['p50_ms']:.2f} ms, "
-            f"p99 {line['serving']['p99_ms']:.2f} ms")
+            f"p99 {line['serving']['p99_ms']:.2f} ms at the highest rate")
     if calib is not None:
         line["calibration"] = calib
     if not args.no_cpu_baseline:

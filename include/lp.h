@@ -287,24 +287,27 @@ int lp_ir_decide(const double *h, int len, int corrections, int max_iter);
  * batching).  Each request is solved as lu_factor + lu_solve (LP_FP64) or as
  * lu_solve_ir (binary32 factors + binary64 refinement, LP_FP32/BF16/FP16),
  * and checked with residual_check.  lp_server_create allocates the server's
- * device memory pool (memory_bytes) once -- the one allocating call of this
- * library; per-request workspaces come from that pool.  Admission is first
- * come, first served, by device footprint (lp_request_footprint) and free
- * launch slots.  Requests with n <= small_n_max run batched: one launch per
- * batch of up to max_batch requests, one workgroup per request at a time
- * (batch_workgroups workgroups pull requests from the batch); for those the
- * low-precision route factors in binary32.  Larger requests run the blocked
- * path on their own stream (large_slots at once).  Up to batch_slots batches
- * run concurrently.  A result depends only on the request (size, precision,
- * data), never on what else was in flight.  Not thread-safe: one thread drives
- * a server.  The caller keeps A, B and X (device memory) alive until the
- * request's ticket is returned by lp_server_poll. */
+ * device memory pool (memory_bytes) and its pinned host ring once -- the one
+ * allocating call of this library; per-request workspaces come from that
+ * pool.  Admission is first come, first served, by device footprint
+ * (lp_request_footprint).  Requests with n <= small_n_max are published into
+ * a ring of up to max_batch descriptors in pinned host memory; a persistent
+ * batched kernel of batch_workgroups workgroups pulls them, one workgroup per
+ * request, each request completing on its own (for those the low-precision
+ * route factors in binary32).  The kernel exits after 2 ms without requests
+ * and is launched again when one arrives.  Larger requests run the blocked
+ * path on their own stream (large_slots at once).  A result depends only on
+ * the request (size, precision, data), never on what else was in flight.
+ * Not thread-safe: one thread drives a server.  The caller keeps A, B and X
+ * (device memory) alive until the request's ticket is returned by
+ * lp_server_poll.  lp_server_destroy stops the kernel and waits for the
+ * server's own streams and worker threads (not the whole device). */
 typedef struct {
   size_t memory_bytes;  /* device pool size                                     */
   int small_n_max;      /* n at or below which requests are batched (<= 2048)    */
-  int max_batch;        /* requests per batched launch (<= 4096)                 */
-  int batch_slots;      /* batched launches in flight at once (1..64)            */
-  int batch_workgroups; /* workgroups per batched launch                         */
+  int max_batch;        /* ring capacity: batched requests in flight (<= 4096)   */
+  int batch_slots;      /* kept for compatibility (1..64); not used              */
+  int batch_workgroups; /* workgroups of the persistent batched kernel           */
   int large_slots;      /* blocked-path requests in flight at once (0..64)       */
 } lp_server_cfg;
 
@@ -328,6 +331,9 @@ typedef struct {
   int batched;           /* 1 if it ran in a batched launch                      */
   double scaled_residual;/* max over right-hand sides                            */
   double latency_ms;     /* submit -> seen complete by lp_server_poll            */
+  double device_ms;      /* the request's own device time (batched: its
+                            workgroup, device clock; blocked: events around its
+                            work); latency_ms - device_ms is the time it waited */
 } lp_result;
 
 typedef struct lp_server lp_server;

@@ -85,7 +85,7 @@ class Result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("info", ctypes.c_int),
                 ("iterations", ctypes.c_int), ("fell_back", ctypes.c_int),
                 ("batched", ctypes.c_int), ("scaled_residual", ctypes.c_double),
-                ("latency_ms", ctypes.c_double)]
+                ("latency_ms", ctypes.c_double), ("device_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -336,8 +336,8 @@ class Server:
     kept alive here until its result has been returned.
     """
 
-    def __init__(self, memory_bytes: int, small_n_max: int = 512, max_batch: int = 256,
-                 batch_slots: int = 4, batch_workgroups: int = 512, large_slots: int = 4):
+    def __init__(self, memory_bytes: int, small_n_max: int = 128, max_batch: int = 256,
+                 batch_slots: int = 4, batch_workgroups: int = 32, large_slots: int = 4):
         self.cfg = ServerCfg(memory_bytes, small_n_max, max_batch, batch_slots,
                              batch_workgroups, large_slots)
         h = ctypes.c_void_p()

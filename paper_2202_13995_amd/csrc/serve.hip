@@ -7,16 +7,29 @@
 // Linpack") and checked with the benchmark's scaled residual.
 //
 // Runtime (host, poll-driven): lp_server_submit queues a request; every
-// lp_server_poll call (1) retires finished work (event queries), (2) admits
-// queued requests first-come-first-served while their device footprint fits
-// the free part of the server's memory pool and a launch slot is free, and
-// (3) launches: requests with n <= small_n_max go into one batched launch
-// (one workgroup per request, requests pulled through an atomic counter so
-// uneven sizes balance), larger ones run the blocked path (lu_factor /
-// lu_solve_ir) on a stream of their own.  Several batches and large requests
-// run at once on different streams, so requests arriving while others are on
-// the GPU start as soon as memory and a slot are free.  A request's arithmetic
-// depends only on its size and precision, never on what it is batched with.
+// lp_server_poll call (1) retires finished work, (2) admits queued requests
+// first-come-first-served while their device footprint fits the free part of
+// the server's memory pool, and (3) hands them to the device: requests with
+// n <= small_n_max are published into a ring of descriptors in pinned host
+// memory, from which a persistent batched kernel pulls them (one workgroup per
+// request, a workgroup takes the next published request as soon as it is free,
+// so uneven sizes balance and every request completes on its own); larger ones
+// run the blocked path (lu_factor / lu_solve_ir) on a stream of their own.
+// Requests arriving while others are on the GPU start as soon as memory and a
+// workgroup or slot are free.  A request's arithmetic depends only on its size
+// and precision, never on what else is in flight.
+//
+// The ring protocol: the host writes a descriptor into slot (k mod capacity),
+// then advances the published count with a release store; a workgroup claims
+// index k only when k is below the published count (compare-and-swap on a
+// device counter), so no claim ever waits for a request that does not exist.
+// It reads the descriptor with system-scope loads, solves, writes the results
+// with system-scope stores and then the slot's completion word (k + 1) with a
+// release store, which the host polls.  The kernel exits when the host sets
+// its stop word or after a spell without requests (so every launch drains);
+// the host launches it again when a request is published and it is not
+// running.  Requests are published only after the work their submitter's
+// stream had queued has completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -225,115 +238,180 @@ __host__ __device__ inline size_t small_ws_bytes(int n, int nrhs, int prec) {
   return off;
 }
 
-__global__ __launch_bounds__(kST) void batched_solve_kernel(const SmallReq* __restrict__ reqs,
-                                                            int count,
-                                                            unsigned* __restrict__ next) {
-  __shared__ double red[kST / 64];
-  __shared__ int redi[kST / 64];
-  __shared__ int s_job;
-  for (;;) {
-    if (threadIdx.x == 0) s_job = (int)atomicAdd(next, 1u);
+// One request, by the whole workgroup; res[0..4] = {status, info, scaled
+// residual, iterations, fell_back} (res[5]: its device time, set by the caller).
+constexpr int kResWords = 6;
+__device__ void solve_small(const SmallReq& q, double* res, double* red, int* redi) {
+  const int n = q.n, nrhs = q.nrhs;
+  char* w = (char*)q.W;
+  const size_t el = (q.prec == LP_FP64) ? 8 : 4;
+  size_t off = (el * (size_t)n * n + 255) & ~(size_t)255;
+  int32_t* ipiv = (int32_t*)(w + off);
+  int32_t* perm = ipiv + n;
+  off = (off + 8 * (size_t)n + 255) & ~(size_t)255;
+  double status = 0.0, iters = 0.0, fell = 0.0, sres = 0.0;
+  int info = 0;
+  const double anorm = wg_anorm(n, q.A, q.lda, red);
+  if (q.prec == LP_FP64) {
+    double* W = (double*)w;
+    for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
+      W[e] = q.A[(e / n) * q.lda + e % n];
     __syncthreads();
-    const int job = s_job;
+    info = wg_getrf<double>(n, W, ipiv, perm, red, redi);
+    for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
+      q.X[(e / nrhs) * q.ldx + e % nrhs] = q.B[(long long)perm[e / nrhs] * q.ldb + e % nrhs];
     __syncthreads();
-    if (job >= count) return;
-    const SmallReq q = reqs[job];
-    const int n = q.n, nrhs = q.nrhs;
-    char* w = (char*)q.W;
-    const size_t el = (q.prec == LP_FP64) ? 8 : 4;
-    size_t off = (el * (size_t)n * n + 255) & ~(size_t)255;
-    int32_t* ipiv = (int32_t*)(w + off);
-    int32_t* perm = ipiv + n;
-    off = (off + 8 * (size_t)n + 255) & ~(size_t)255;
-    double status = 0.0, iters = 0.0, fell = 0.0, sres = 0.0;
-    int info = 0;
-    const double anorm = wg_anorm(n, q.A, q.lda, red);
-    if (q.prec == LP_FP64) {
-      double* W = (double*)w;
-      for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
-        W[e] = q.A[(e / n) * q.lda + e % n];
+    if (info == 0) {
+      wg_getrs<double, double>(n, W, q.X, q.ldx, nrhs);
+      sres = wg_residual(n, q.A, q.lda, q.X, q.ldx, q.B, q.ldb, nrhs, nullptr, red, anorm);
+    } else {
+      status = 1.0;
+    }
+  } else {
+    // binary32 factors, binary64 refinement, binary64 fallback
+    float* W = (float*)w;
+    double* Rv = (double*)(w + off);
+    off = (off + 8 * (size_t)n * nrhs + 255) & ~(size_t)255;
+    float* D = (float*)(w + off);
+    off = (off + 4 * (size_t)n * nrhs + 255) & ~(size_t)255;
+    double* W64 = (double*)(w + off);
+    for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
+      W[e] = (float)q.A[(e / n) * q.lda + e % n];
+    __syncthreads();
+    info = wg_getrf<float>(n, W, ipiv, perm, red, redi);
+    for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
+      D[e] = (float)q.B[(long long)perm[e / nrhs] * q.ldb + e % nrhs];
+    __syncthreads();
+    bool ok = false;
+    if (info == 0) {
+      wg_getrs<float, float>(n, W, D, nrhs, nrhs);
+      for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
+        q.X[(e / nrhs) * q.ldx + e % nrhs] = (double)D[e];
       __syncthreads();
-      info = wg_getrf<double>(n, W, ipiv, perm, red, redi);
+      double h[3] = {0, 0, 0};
+      int hl = 0, k = 0;
+      for (;;) {
+        sres = wg_residual(n, q.A, q.lda, q.X, q.ldx, q.B, q.ldb, nrhs, Rv, red, anorm);
+        h[0] = h[1];
+        h[1] = h[2];
+        h[2] = sres;
+        ++hl;
+        if (sres < 16.0) {
+          ok = true;
+          break;
+        }
+        if (sres != sres || sres > 1.7e308) break;
+        if (hl >= 3 && h[2] > h[1] && h[1] > h[0]) break;
+        if (k >= q.max_iter) break;
+        for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
+          D[e] = (float)Rv[(long long)perm[e / nrhs] * nrhs + e % nrhs];
+        __syncthreads();
+        wg_getrs<float, float>(n, W, D, nrhs, nrhs);
+        for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
+          q.X[(e / nrhs) * q.ldx + e % nrhs] += (double)D[e];
+        __syncthreads();
+        ++k;
+      }
+      iters = k;
+    }
+    if (!ok) {
+      fell = 1.0;
+      for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
+        W64[e] = q.A[(e / n) * q.lda + e % n];
+      __syncthreads();
+      const int info64 = wg_getrf<double>(n, W64, ipiv, perm, red, redi);
       for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
         q.X[(e / nrhs) * q.ldx + e % nrhs] = q.B[(long long)perm[e / nrhs] * q.ldb + e % nrhs];
       __syncthreads();
-      if (info == 0) {
-        wg_getrs<double, double>(n, W, q.X, q.ldx, nrhs);
+      if (info64 == 0) {
+        wg_getrs<double, double>(n, W64, q.X, q.ldx, nrhs);
         sres = wg_residual(n, q.A, q.lda, q.X, q.ldx, q.B, q.ldb, nrhs, nullptr, red, anorm);
       } else {
         status = 1.0;
-      }
-    } else {
-      // binary32 factors, binary64 refinement, binary64 fallback
-      float* W = (float*)w;
-      double* Rv = (double*)(w + off);
-      off = (off + 8 * (size_t)n * nrhs + 255) & ~(size_t)255;
-      float* D = (float*)(w + off);
-      off = (off + 4 * (size_t)n * nrhs + 255) & ~(size_t)255;
-      double* W64 = (double*)(w + off);
-      for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
-        W[e] = (float)q.A[(e / n) * q.lda + e % n];
-      __syncthreads();
-      info = wg_getrf<float>(n, W, ipiv, perm, red, redi);
-      for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
-        D[e] = (float)q.B[(long long)perm[e / nrhs] * q.ldb + e % nrhs];
-      __syncthreads();
-      bool ok = false;
-      if (info == 0) {
-        wg_getrs<float, float>(n, W, D, nrhs, nrhs);
-        for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
-          q.X[(e / nrhs) * q.ldx + e % nrhs] = (double)D[e];
-        __syncthreads();
-        double h[3] = {0, 0, 0};
-        int hl = 0, k = 0;
-        for (;;) {
-          sres = wg_residual(n, q.A, q.lda, q.X, q.ldx, q.B, q.ldb, nrhs, Rv, red, anorm);
-          h[0] = h[1];
-          h[1] = h[2];
-          h[2] = sres;
-          ++hl;
-          if (sres < 16.0) {
-            ok = true;
-            break;
-          }
-          if (sres != sres || sres > 1.7e308) break;
-          if (hl >= 3 && h[2] > h[1] && h[1] > h[0]) break;
-          if (k >= q.max_iter) break;
-          for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
-            D[e] = (float)Rv[(long long)perm[e / nrhs] * nrhs + e % nrhs];
-          __syncthreads();
-          wg_getrs<float, float>(n, W, D, nrhs, nrhs);
-          for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
-            q.X[(e / nrhs) * q.ldx + e % nrhs] += (double)D[e];
-          __syncthreads();
-          ++k;
-        }
-        iters = k;
-      }
-      if (!ok) {
-        fell = 1.0;
-        for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
-          W64[e] = q.A[(e / n) * q.lda + e % n];
-        __syncthreads();
-        const int info64 = wg_getrf<double>(n, W64, ipiv, perm, red, redi);
-        for (long long e = threadIdx.x; e < (long long)n * nrhs; e += kST)
-          q.X[(e / nrhs) * q.ldx + e % nrhs] = q.B[(long long)perm[e / nrhs] * q.ldb + e % nrhs];
-        __syncthreads();
-        if (info64 == 0) {
-          wg_getrs<double, double>(n, W64, q.X, q.ldx, nrhs);
-          sres = wg_residual(n, q.A, q.lda, q.X, q.ldx, q.B, q.ldb, nrhs, nullptr, red, anorm);
-        } else {
-          status = 1.0;
-          info = info64;
-        }
+        info = info64;
       }
     }
+  }
+  res[0] = status;
+  res[1] = (double)info;
+  res[2] = sres;
+  res[3] = iters;
+  res[4] = fell;
+}
+
+// The ring of descriptors shared with the host (pinned, device-visible).
+struct RingShared {
+  unsigned long long published;  // requests written so far (host, release)
+  unsigned long long stop;       // host: set to make the kernel exit
+};
+
+// A workgroup leaves after 2 ms (100 MHz clock) without a request, so an idle
+// server holds no compute units; between looks at the host's counter it
+// sleeps about 4 us, which keeps the polling traffic over PCIe small.
+constexpr unsigned long long kIdleTicks = 200000ull;
+
+__device__ __forceinline__ unsigned long long sys_load(const unsigned long long* p) {
+  return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_ACQUIRE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(kST) void ring_solve_kernel(const SmallReq* __restrict__ ring,
+                                                         double* __restrict__ results,
+                                                         unsigned long long* __restrict__ done,
+                                                         const RingShared* __restrict__ shared,
+                                                         unsigned long long* __restrict__ head,
+                                                         int capacity) {
+  __shared__ double red[kST / 64];
+  __shared__ int redi[kST / 64];
+  __shared__ long long s_job;
+  __shared__ unsigned long long s_desc[(sizeof(SmallReq) + 7) / 8];
+  for (;;) {
     if (threadIdx.x == 0) {
-      q.result[0] = status;
-      q.result[1] = (double)info;
-      q.result[2] = sres;
-      q.result[3] = iters;
-      q.result[4] = fell;
+      long long job = -1;
+      unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      for (;;) {
+        unsigned long long h =
+            __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long pub = sys_load(&shared->published);
+        if (h < pub) {
+          if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            job = (long long)h;
+            break;
+          }
+          continue;  // another workgroup took it: look again at once
+        }
+        if (sys_load(&shared->stop) != 0ull) break;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kIdleTicks) break;
+        __builtin_amdgcn_s_sleep(64);
+      }
+      if (job >= 0) {
+        // the descriptor: system-scope loads after the acquire of `published`
+        const unsigned long long* src =
+            reinterpret_cast<const unsigned long long*>(ring + (job % capacity));
+        for (int w = 0; w < (int)((sizeof(SmallReq) + 7) / 8); ++w)
+          s_desc[w] = __hip_atomic_load(const_cast<unsigned long long*>(src + w), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      s_job = job;
+    }
+    __syncthreads();
+    const long long job = s_job;
+    if (job < 0) return;
+    const SmallReq q = *reinterpret_cast<const SmallReq*>(s_desc);
+    double res[kResWords];
+    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
+    solve_small(q, res, red, redi);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int slot = (int)(job % capacity);
+      // the request's own device time (100 MHz clock), apart from its wait
+      res[5] = (double)(__builtin_amdgcn_s_memrealtime() - t_start) * 1e-5;
+      for (int k = 0; k < kResWords; ++k)
+        __hip_atomic_store(&results[kResWords * slot + k], res[k], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&done[slot], (unsigned long long)job + 1ull, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();
   }
@@ -341,19 +419,6 @@ __global__ __launch_bounds__(kST) void batched_solve_kernel(const SmallReq* __re
 
 // ------------------------------------------------------------ host runtime
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// One batched launch's block in the pool: max_batch descriptors, the job
-// counter (own 256-byte line), then 5 result doubles per request.
-struct DescLayout {
-  size_t counter, results, total;
-};
-DescLayout desc_layout(int max_batch) {
-  DescLayout d;
-  d.counter = align256(sizeof(SmallReq) * (size_t)max_batch);
-  d.results = d.counter + 256;
-  d.total = d.results + align256(sizeof(double) * 5 * (size_t)max_batch);
-  return d;
-}
 
 struct Block {
   size_t off, size;
@@ -428,20 +493,31 @@ struct lp_server {
     hipEvent_t ready;  // recorded on the submitter's stream; the request's work waits on it
   };
   std::deque<Pending> queue;
-  struct Batch {
-    hipStream_t s;
-    hipEvent_t done;
-    bool busy = false;
-    lp::Block desc;  // descriptors + counter + results in the pool
-    std::vector<Pending> members;
-    std::vector<lp::Block> ws;
-    lp::SmallReq* host_desc = nullptr;  // pinned staging for descriptors
-    double* host_res = nullptr;         // pinned results
-  };
-  std::vector<Batch> batches;
+  // the batched path: a ring of descriptors in pinned host memory and the
+  // persistent kernel that pulls from it
+  struct Ring {
+    int capacity = 0;
+    lp::SmallReq* desc = nullptr;       // pinned: capacity descriptors
+    double* results = nullptr;          // pinned: kResWords per slot
+    unsigned long long* done = nullptr; // pinned: completion word per slot (job + 1)
+    lp::RingShared* shared = nullptr;   // pinned: published count, stop word
+    unsigned long long* head = nullptr; // device (in the pool): claimed count
+    unsigned long long published = 0;   // host copy
+    hipStream_t s = nullptr;
+    hipEvent_t exited = nullptr;        // recorded after each launch of the kernel
+    bool launched = false;
+    struct Slot {
+      bool used = false;
+      unsigned long long job = 0;
+      Pending member;
+      lp::Block ws;
+    };
+    std::vector<Slot> slots;
+    int in_flight = 0;
+  } ring;
   struct Large {
     hipStream_t s;
-    hipEvent_t done;
+    hipEvent_t start, done;         // around the request's work on s (timing)
     bool busy = false;
     bool threaded = false;          // refinement runs on a worker thread
     std::thread worker;
@@ -468,6 +544,7 @@ size_t request_footprint(const lp_server_cfg& cfg, const lp_request& r) {
     size_t f = lp::align256(sizeof(double) * (size_t)r.n * r.n);  // factors
     f += lp::align256(lu_workspace_bytes(r.n, r.nb, LP_FP64));
     f += lp::align256(4 * (size_t)r.n) + 256 + lp::align256(sizeof(double) * 5 * r.nrhs);
+    f += lp::align256(lu_solve_workspace_bytes(r.n, LP_FP64, r.nrhs));
     return f;
   }
   return lp::align256(lu_solve_ir_workspace_bytes(r.n, r.nb, r.prec, r.nrhs));
@@ -487,6 +564,9 @@ int validate(const lp_request* r) {
 
 }  // namespace
 
+// The ring's device counter lives in the first 256 bytes of the pool.
+constexpr size_t kPoolReserve = 256;
+
 extern "C" {
 
 int lp_server_create(const lp_server_cfg* cfg, lp_server** out) {
@@ -505,24 +585,37 @@ int lp_server_create(const lp_server_cfg* cfg, lp_server** out) {
     delete sv;
     return LP_EHIP_BASE - (int)e;
   }
-  sv->pool.init((char*)sv->dev, cfg->memory_bytes);
-  sv->batches.resize(cfg->batch_slots);
-  for (auto& b : sv->batches) {
-    if (hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&b.host_desc, sizeof(lp::SmallReq) * cfg->max_batch,
-                      hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&b.host_res, sizeof(double) * 5 * cfg->max_batch,
-                      hipHostMallocDefault) != hipSuccess) {
-      lp_server_destroy(sv);
-      return LP_EHIP_BASE - (int)hipErrorOutOfMemory;
-    }
+  sv->pool.init((char*)sv->dev + kPoolReserve, cfg->memory_bytes - kPoolReserve);
+  lp_server::Ring& rg = sv->ring;
+  rg.capacity = cfg->max_batch;
+  rg.slots.resize(rg.capacity);
+  rg.head = (unsigned long long*)sv->dev;
+  const unsigned mf = hipHostMallocMapped | hipHostMallocCoherent;
+  if (hipHostMalloc((void**)&rg.desc, sizeof(lp::SmallReq) * rg.capacity, mf) != hipSuccess ||
+      hipHostMalloc((void**)&rg.results, sizeof(double) * lp::kResWords * rg.capacity, mf) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&rg.done, sizeof(unsigned long long) * rg.capacity, mf) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&rg.shared, sizeof(lp::RingShared), mf) != hipSuccess ||
+      hipStreamCreateWithFlags(&rg.s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&rg.exited, hipEventDisableTiming) != hipSuccess) {
+    lp_server_destroy(sv);
+    return LP_EHIP_BASE - (int)hipErrorOutOfMemory;
+  }
+  std::memset(rg.done, 0, sizeof(unsigned long long) * rg.capacity);
+  rg.shared->published = 0;
+  rg.shared->stop = 0;
+  int rc = lp::launch_zero_words(rg.head, 2, rg.s);
+  if (rc == LP_OK && hipStreamSynchronize(rg.s) != hipSuccess) rc = LP_EHIP_BASE;
+  if (rc != LP_OK) {
+    lp_server_destroy(sv);
+    return rc;
   }
   for (int i = 0; i < cfg->large_slots; ++i) sv->larges.emplace_back(new lp_server::Large());
   for (auto& lp_ : sv->larges) {
     lp_server::Large& l = *lp_;
     if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.done) != hipSuccess ||
         hipHostMalloc((void**)&l.info_host, 16, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&l.res_host, sizeof(double) * 5 * 64, hipHostMallocDefault) !=
             hipSuccess) {
@@ -537,22 +630,30 @@ int lp_server_create(const lp_server_cfg* cfg, lp_server** out) {
 
 int lp_server_destroy(lp_server* sv) {
   if (sv == nullptr) return -1;
-  (void)hipDeviceSynchronize();
-  for (auto& b : sv->batches) {
-    if (b.s) (void)hipStreamDestroy(b.s);
-    if (b.done) (void)hipEventDestroy(b.done);
-    if (b.host_desc) (void)hipHostFree(b.host_desc);
-    if (b.host_res) (void)hipHostFree(b.host_res);
-  }
+  lp_server::Ring& rg = sv->ring;
+  // stop the persistent kernel and wait for the server's own streams only
+  if (rg.shared) __atomic_store_n(&rg.shared->stop, 1ull, __ATOMIC_RELEASE);
+  if (rg.s) (void)hipStreamSynchronize(rg.s);
   for (auto& lp_ : sv->larges) {
     lp_server::Large& l = *lp_;
     if (l.threaded && l.worker.joinable()) l.worker.join();
+    if (l.s) (void)hipStreamSynchronize(l.s);
+  }
+  if (rg.s) (void)hipStreamDestroy(rg.s);
+  if (rg.exited) (void)hipEventDestroy(rg.exited);
+  for (void* h : {(void*)rg.desc, (void*)rg.results, (void*)rg.done, (void*)rg.shared})
+    if (h) (void)hipHostFree(h);
+  for (auto& lp_ : sv->larges) {
+    lp_server::Large& l = *lp_;
     if (l.s) (void)hipStreamDestroy(l.s);
+    if (l.start) (void)hipEventDestroy(l.start);
     if (l.done) (void)hipEventDestroy(l.done);
     if (l.info_host) (void)hipHostFree(l.info_host);
     if (l.res_host) (void)hipHostFree(l.res_host);
   }
   for (auto& p : sv->queue) (void)hipEventDestroy(p.ready);
+  for (auto& sl : rg.slots)
+    if (sl.used) (void)hipEventDestroy(sl.member.ready);
   if (sv->dev) (void)hipFree(sv->dev);
   delete sv;
   return LP_OK;
@@ -565,8 +666,7 @@ int lp_server_submit(lp_server* sv, const lp_request* req, uint64_t* ticket, voi
   if (ticket == nullptr) return -3;
   if (req->n > sv->cfg.small_n_max && sv->cfg.large_slots == 0) return LP_ENOTSUP;
   const size_t foot = request_footprint(sv->cfg, *req);
-  const size_t desc_reserve = lp::desc_layout(sv->cfg.max_batch).total;
-  if (foot + desc_reserve > sv->cfg.memory_bytes) return LP_ENOSPC;  // can never fit
+  if (foot > sv->cfg.memory_bytes - kPoolReserve) return LP_ENOSPC;  // can never fit
   lp_server::Pending p;
   LP_HIP_TRY(hipEventCreateWithFlags(&p.ready, hipEventDisableTiming));
   const hipError_t e = hipEventRecord(p.ready, (hipStream_t)stream);
@@ -583,179 +683,173 @@ int lp_server_submit(lp_server* sv, const lp_request* req, uint64_t* ticket, voi
   return LP_OK;
 }
 
+static void finish(lp_server* sv, const lp_server::Pending& m, int status, int info, double sres,
+                   int iters, int fell, int batched, double device_ms) {
+  lp_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.device_ms = device_ms;
+  r.ticket = m.ticket;
+  r.status = status;
+  r.info = info;
+  r.scaled_residual = sres;
+  r.iterations = iters;
+  r.fell_back = fell;
+  r.batched = batched;
+  r.latency_ms = lp::now_ms() - m.t_submit;
+  sv->finished.push_back(r);
+  (void)hipEventDestroy(m.ready);
+}
+
 static int retire(lp_server* sv) {
-  for (auto& b : sv->batches) {
-    if (!b.busy) continue;
-    const hipError_t q = hipEventQuery(b.done);
-    if (q == hipErrorNotReady) continue;
-    if (q != hipSuccess) return LP_EHIP_BASE - (int)q;
-    const double t = lp::now_ms();
-    for (size_t i = 0; i < b.members.size(); ++i) {
-      lp_result r;
-      std::memset(&r, 0, sizeof(r));
-      r.ticket = b.members[i].ticket;
-      r.status = (int)b.host_res[5 * i + 0];
-      r.info = (int)b.host_res[5 * i + 1];
-      r.scaled_residual = b.host_res[5 * i + 2];
-      r.iterations = (int)b.host_res[5 * i + 3];
-      r.fell_back = (int)b.host_res[5 * i + 4];
-      r.batched = 1;
-      r.latency_ms = t - b.members[i].t_submit;
-      sv->finished.push_back(r);
-      sv->pool.release(b.ws[i]);
-      (void)hipEventDestroy(b.members[i].ready);
-    }
-    sv->pool.release(b.desc);
-    b.members.clear();
-    b.ws.clear();
-    b.busy = false;
+  lp_server::Ring& rg = sv->ring;
+  for (int i = 0; i < rg.capacity && rg.in_flight > 0; ++i) {
+    lp_server::Ring::Slot& sl = rg.slots[i];
+    if (!sl.used) continue;
+    if (__atomic_load_n(&rg.done[i], __ATOMIC_ACQUIRE) != sl.job + 1) continue;
+    const double* rr = rg.results + lp::kResWords * i;
+    finish(sv, sl.member, (int)rr[0], (int)rr[1], rr[2], (int)rr[3], (int)rr[4], 1, rr[5]);
+    sv->pool.release(sl.ws);
+    sl.used = false;
+    --rg.in_flight;
   }
   for (auto& lp_ : sv->larges) {
     lp_server::Large& l = *lp_;
     if (!l.busy) continue;
-    if (l.threaded) {
-      if (!l.finished.load(std::memory_order_acquire)) continue;
-      l.worker.join();
-      l.threaded = false;
-    } else {
-      const hipError_t q = hipEventQuery(l.done);
-      if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess) return LP_EHIP_BASE - (int)q;
-    }
-    lp_result r;
-    std::memset(&r, 0, sizeof(r));
-    r.ticket = l.member.ticket;
-    r.latency_ms = lp::now_ms() - l.member.t_submit;
+    if (!l.finished.load(std::memory_order_acquire)) continue;
+    l.worker.join();
+    l.threaded = false;
     if (l.member.req.prec == LP_FP64) {
-      r.info = *l.info_host;
-      r.status = (l.rc != LP_OK || r.info != 0) ? 1 : 0;
+      const int info = (l.rc == LP_OK) ? *l.info_host : 0;
       double m = 0.0;
       for (int c = 0; c < l.member.req.nrhs; ++c) {
         const double v = l.res_host[5 * c];
         if (!(v <= m)) m = v;
       }
-      r.scaled_residual = m;
+      float ms = -1.0f;
+      if (l.rc != LP_OK || hipEventElapsedTime(&ms, l.start, l.done) != hipSuccess) ms = -1.0f;
+      if (l.rc != LP_OK) m = NAN;
+      finish(sv, l.member, (l.rc != LP_OK || info != 0) ? 1 : 0, info, m, 0, 0, 0, ms);
     } else {
-      r.info = l.rep.info;
-      r.status = (l.rc != LP_OK || !l.rep.converged) ? 1 : 0;
-      r.scaled_residual = l.rep.scaled_residual;
-      r.iterations = l.rep.iterations;
-      r.fell_back = l.rep.fell_back;
+      finish(sv, l.member, (l.rc != LP_OK || !l.rep.converged) ? 1 : 0, l.rep.info,
+             l.rep.scaled_residual, l.rep.iterations, l.rep.fell_back, 0, l.rep.t_total_ms);
     }
-    sv->finished.push_back(r);
     sv->pool.release(l.ws);
-    (void)hipEventDestroy(l.member.ready);
     l.busy = false;
   }
   return LP_OK;
 }
 
+// The blocked-path work of one large request runs on a worker thread with the
+// slot's stream (it issues many launches, and the refinement takes host
+// decisions), so the poll loop keeps admitting and publishing other work.  A
+// failure is reported as a failed request (status 1), never stranded; the
+// request's memory returns to the pool at retirement either way.
+static void run_large_fp64(lp_server::Large* l, const lp_request r, char* base,
+                           hipEvent_t ready) {
+  hipStream_t s = l->s;
+  size_t off = 0;
+  double* F = (double*)(base + off);
+  off += lp::align256(sizeof(double) * (size_t)r.n * r.n);
+  void* fw = base + off;
+  const size_t fwb = lu_workspace_bytes(r.n, r.nb, LP_FP64);
+  off += lp::align256(fwb);
+  int32_t* ipiv = (int32_t*)(base + off);
+  off += lp::align256(4 * (size_t)r.n);
+  int32_t* info = (int32_t*)(base + off);
+  off += 256;
+  double* out = (double*)(base + off);
+  off += lp::align256(sizeof(double) * 5 * r.nrhs);
+  void* sw = base + off;
+  const size_t swb = lu_solve_workspace_bytes(r.n, LP_FP64, r.nrhs);
+  int rc = LP_OK;
+  auto hip = [&](hipError_t e) {
+    if (rc == LP_OK && e != hipSuccess) rc = LP_EHIP_BASE - (int)e;
+  };
+  hip(hipStreamWaitEvent(s, ready, 0));
+  if (rc == LP_OK) hip(hipEventRecord(l->start, s));
+  if (rc == LP_OK)
+    hip(hipMemcpy2DAsync(F, sizeof(double) * r.n, r.A, sizeof(double) * r.lda,
+                         sizeof(double) * r.n, r.n, hipMemcpyDeviceToDevice, s));
+  if (rc == LP_OK)
+    hip(hipMemcpy2DAsync(r.X, sizeof(double) * r.ldx, r.B, sizeof(double) * r.ldb,
+                         sizeof(double) * r.nrhs, r.n, hipMemcpyDeviceToDevice, s));
+  if (rc == LP_OK) rc = lu_factor(r.n, r.nb, LP_FP64, F, r.n, ipiv, info, fw, fwb, s);
+  if (rc == LP_OK)
+    rc = lu_solve_ex(r.n, LP_FP64, F, r.n, ipiv, info, r.X, r.ldx, r.nrhs, nullptr, sw, swb, s);
+  if (rc == LP_OK) rc = residual_check(r.n, r.A, r.lda, r.X, r.ldx, r.B, r.ldb, r.nrhs, out, s);
+  if (rc == LP_OK) hip(hipMemcpyAsync(l->info_host, info, 4, hipMemcpyDeviceToHost, s));
+  if (rc == LP_OK)
+    hip(hipMemcpyAsync(l->res_host, out, sizeof(double) * 5 * r.nrhs, hipMemcpyDeviceToHost, s));
+  if (rc == LP_OK) hip(hipEventRecord(l->done, s));
+  // whatever was queued runs to completion before the memory can be reused
+  hip(hipStreamSynchronize(s));
+  l->rc = rc;
+}
+
 static int launch_large(lp_server* sv, lp_server::Large& l, const lp_server::Pending& p,
                         const Block& ws) {
-  const lp_request& r = p.req;
-  char* base = (char*)sv->dev + ws.off;
+  const lp_request r = p.req;
+  char* base = (char*)sv->dev + kPoolReserve + ws.off;
   l.member = p;
   l.ws = ws;
-  l.busy = true;
   l.rc = LP_OK;
-  hipStream_t s = l.s;
-  LP_HIP_TRY(hipStreamWaitEvent(s, p.ready, 0));
-  if (r.prec == LP_FP64) {
-    size_t off = 0;
-    double* F = (double*)(base + off);
-    off += lp::align256(sizeof(double) * (size_t)r.n * r.n);
-    void* fw = base + off;
-    const size_t fwb = lu_workspace_bytes(r.n, r.nb, LP_FP64);
-    off += lp::align256(fwb);
-    int32_t* ipiv = (int32_t*)(base + off);
-    off += lp::align256(4 * (size_t)r.n);
-    int32_t* info = (int32_t*)(base + off);
-    off += 256;
-    double* out = (double*)(base + off);
-    LP_HIP_TRY(hipMemcpy2DAsync(F, sizeof(double) * r.n, r.A, sizeof(double) * r.lda,
-                                sizeof(double) * r.n, r.n, hipMemcpyDeviceToDevice, s));
-    LP_HIP_TRY(hipMemcpy2DAsync(r.X, sizeof(double) * r.ldx, r.B, sizeof(double) * r.ldb,
-                                sizeof(double) * r.nrhs, r.n, hipMemcpyDeviceToDevice, s));
-    int rc = lu_factor(r.n, r.nb, LP_FP64, F, r.n, ipiv, info, fw, fwb, s);
-    if (rc == LP_OK) rc = lu_solve(r.n, LP_FP64, F, r.n, ipiv, info, r.X, r.ldx, r.nrhs, nullptr, s);
-    if (rc == LP_OK)
-      rc = residual_check(r.n, r.A, r.lda, r.X, r.ldx, r.B, r.ldb, r.nrhs, out, s);
-    l.rc = rc;
-    LP_HIP_TRY(hipMemcpyAsync(l.info_host, info, 4, hipMemcpyDeviceToHost, s));
-    LP_HIP_TRY(hipMemcpyAsync(l.res_host, out, sizeof(double) * 5 * r.nrhs,
-                              hipMemcpyDeviceToHost, s));
-    LP_HIP_TRY(hipEventRecord(l.done, s));
-  } else {
-    // refinement takes host decisions (it synchronizes its own stream), so it
-    // runs on a worker thread and the poll loop keeps admitting other work
-    l.finished.store(0, std::memory_order_relaxed);
-    l.threaded = true;
-    lp_server::Large* lpt = &l;
-    const int maxit = r.max_iter > 0 ? r.max_iter : 30;
-    const size_t wsb = ws.size;
-    l.worker = std::thread([lpt, r, base, maxit, wsb]() {
-      lpt->rc = lu_solve_ir(r.n, r.nb, r.prec, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, r.nrhs, maxit,
-                            base, wsb, &lpt->rep, lpt->s);
-      lpt->finished.store(1, std::memory_order_release);
-    });
-  }
-  return LP_OK;
-}
-
-// Admission: walk the queue in arrival order.  A large request that has no
-// free slot is skipped (small ones may pass it); one that does not fit the
-// free memory stops admission, so it is not starved by later arrivals.  Small
-// requests fill batches (as many batches as slots are free).
-static int launch_batch(lp_server* sv, lp_server::Batch& b, std::vector<lp::SmallReq>& descs,
-                        const Block& dblk) {
-  char* dbase = (char*)sv->dev + dblk.off;
-  const int cnt = (int)descs.size();
-  const lp::DescLayout dl = lp::desc_layout(sv->cfg.max_batch);
-  if (cnt < 1 || cnt > sv->cfg.max_batch || dblk.size < dl.total) return LP_ENOSPC;
-  double* res_dev = (double*)(dbase + dl.results);
-  unsigned* counter = (unsigned*)(dbase + dl.counter);
-  for (int i = 0; i < cnt; ++i) {
-    descs[i].result = res_dev + 5 * i;
-    b.host_desc[i] = descs[i];
-  }
-  b.desc = dblk;
-  b.busy = true;
-  hipStream_t s = b.s;
-  for (const auto& m : b.members) LP_HIP_TRY(hipStreamWaitEvent(s, m.ready, 0));
-  LP_HIP_TRY(hipMemcpyAsync(dbase, b.host_desc, sizeof(lp::SmallReq) * cnt, hipMemcpyHostToDevice,
-                            s));
-  int rc = lp::launch_zero_words(counter, 1, s);
-  if (rc != LP_OK) return rc;
-  const int wgs = std::min(cnt, sv->cfg.batch_workgroups);
-  hipLaunchKernelGGL(lp::batched_solve_kernel, dim3(wgs), dim3(lp::kST), 0, s,
-                     (const lp::SmallReq*)dbase, cnt, counter);
-  LP_LAUNCH_CHECK();
-  LP_HIP_TRY(hipMemcpyAsync(b.host_res, res_dev, sizeof(double) * 5 * cnt, hipMemcpyDeviceToHost,
-                            s));
-  LP_HIP_TRY(hipEventRecord(b.done, s));
-  return LP_OK;
-}
-
-static int admit_and_launch(lp_server* sv) {
-  const size_t desc_bytes = lp::desc_layout(sv->cfg.max_batch).total;
-  lp_server::Batch* batch = nullptr;
-  std::vector<lp::SmallReq> descs;
-  Block dblk{0, 0};
-  auto flush = [&]() -> int {
-    int rc = LP_OK;
-    if (batch != nullptr) {
-      if (!descs.empty())
-        rc = launch_batch(sv, *batch, descs, dblk);
-      else
-        sv->pool.release(dblk);
+  l.finished.store(0, std::memory_order_relaxed);
+  l.threaded = true;
+  l.busy = true;
+  lp_server::Large* lpt = &l;
+  const int maxit = r.max_iter > 0 ? r.max_iter : 30;
+  const size_t wsb = ws.size;
+  const hipEvent_t ready = p.ready;
+  l.worker = std::thread([lpt, r, base, maxit, wsb, ready]() {
+    if (r.prec == LP_FP64) {
+      run_large_fp64(lpt, r, base, ready);
+    } else {
+      int rc = LP_EHIP_BASE;
+      if (hipStreamWaitEvent(lpt->s, ready, 0) == hipSuccess)
+        rc = lu_solve_ir(r.n, r.nb, r.prec, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, r.nrhs, maxit,
+                         base, wsb, &lpt->rep, lpt->s);
+      lpt->rc = rc;
     }
-    batch = nullptr;
-    descs.clear();
-    return rc;
-  };
+    lpt->finished.store(1, std::memory_order_release);
+  });
+  return LP_OK;
+}
+
+// Make sure the persistent batched kernel is running (it exits after a spell
+// without requests).
+static int ensure_ring_kernel(lp_server* sv) {
+  lp_server::Ring& rg = sv->ring;
+  if (rg.launched) {
+    const hipError_t q = hipEventQuery(rg.exited);
+    if (q == hipErrorNotReady) return LP_OK;
+    if (q != hipSuccess) return LP_EHIP_BASE - (int)q;
+  }
+  const int wgs = std::max(1, std::min(sv->cfg.batch_workgroups, 4 * lp::num_cus()));
+  hipLaunchKernelGGL(lp::ring_solve_kernel, dim3(wgs), dim3(lp::kST), 0, rg.s,
+                     (const lp::SmallReq*)rg.desc, rg.results, rg.done,
+                     (const lp::RingShared*)rg.shared, rg.head, rg.capacity);
+  LP_LAUNCH_CHECK();
+  LP_HIP_TRY(hipEventRecord(rg.exited, rg.s));
+  rg.launched = true;
+  return LP_OK;
+}
+
+// Admission: walk the queue in arrival order.  A request whose submitter's
+// work is still running, or that finds no free ring slot or large-path slot,
+// is skipped (later ones may pass it); one that does not fit the free memory
+// stops admission, so it is not starved by later arrivals.
+static int admit_and_launch(lp_server* sv) {
+  lp_server::Ring& rg = sv->ring;
+  bool published = false;
   auto it = sv->queue.begin();
   while (it != sv->queue.end()) {
     const lp_request& r = it->req;
+    const hipError_t q = hipEventQuery(it->ready);
+    if (q == hipErrorNotReady && r.n <= sv->cfg.small_n_max) {
+      ++it;  // the batched kernel cannot wait on a stream: publish once A, B are ready
+      continue;
+    }
+    if (q != hipSuccess && q != hipErrorNotReady) return LP_EHIP_BASE - (int)q;
     if (r.n > sv->cfg.small_n_max) {
       lp_server::Large* slot = nullptr;
       for (auto& l : sv->larges)
@@ -764,7 +858,7 @@ static int admit_and_launch(lp_server* sv) {
           break;
         }
       if (slot == nullptr) {
-        ++it;  // no slot: later small requests may go first
+        ++it;
         continue;
       }
       Block ws;
@@ -775,43 +869,44 @@ static int admit_and_launch(lp_server* sv) {
       if (rc != LP_OK) return rc;
       continue;
     }
-    if (batch != nullptr && (int)batch->members.size() >= sv->cfg.max_batch) {
-      int rc = flush();
-      if (rc != LP_OK) return rc;
+    if (rg.in_flight >= rg.capacity) {
+      ++it;
+      continue;
     }
-    if (batch == nullptr) {
-      for (auto& b : sv->batches)
-        if (!b.busy) {
-          batch = &b;
-          break;
-        }
-      if (batch == nullptr) break;  // every batch slot is busy
-      if (!sv->pool.alloc(desc_bytes, &dblk)) {
-        batch = nullptr;
-        break;
-      }
+    const int slot = (int)(rg.published % (unsigned long long)rg.capacity);
+    if (rg.slots[slot].used) {  // the oldest request in the ring is still running
+      ++it;
+      continue;
     }
     Block ws;
     if (!sv->pool.alloc(it->foot, &ws)) break;
-    lp::SmallReq q;
-    q.A = r.A;
-    q.B = r.B;
-    q.X = r.X;
-    q.W = (char*)sv->dev + ws.off;
-    q.lda = r.lda;
-    q.ldb = r.ldb;
-    q.ldx = r.ldx;
-    q.n = r.n;
-    q.nrhs = r.nrhs;
-    q.prec = r.prec;
-    q.max_iter = r.max_iter > 0 ? r.max_iter : 30;
-    q.result = nullptr;
-    descs.push_back(q);
-    batch->members.push_back(*it);
-    batch->ws.push_back(ws);
+    lp::SmallReq d;
+    d.A = r.A;
+    d.B = r.B;
+    d.X = r.X;
+    d.W = (char*)sv->dev + kPoolReserve + ws.off;
+    d.lda = r.lda;
+    d.ldb = r.ldb;
+    d.ldx = r.ldx;
+    d.n = r.n;
+    d.nrhs = r.nrhs;
+    d.prec = r.prec;
+    d.max_iter = r.max_iter > 0 ? r.max_iter : 30;
+    d.result = nullptr;
+    rg.desc[slot] = d;
+    lp_server::Ring::Slot& sl = rg.slots[slot];
+    sl.used = true;
+    sl.job = rg.published;
+    sl.member = *it;
+    sl.ws = ws;
+    ++rg.in_flight;
+    ++rg.published;
+    __atomic_store_n(&rg.shared->published, rg.published, __ATOMIC_RELEASE);
+    published = true;
     it = sv->queue.erase(it);
   }
-  return flush();
+  if (published || rg.in_flight > 0) return ensure_ring_kernel(sv);
+  return LP_OK;
 }
 
 int lp_server_poll(lp_server* sv, lp_result* done, int cap, int* count) {
@@ -831,8 +926,7 @@ int lp_server_poll(lp_server* sv, lp_result* done, int cap, int* count) {
 
 int lp_server_pending(const lp_server* sv, int* queued, int* running, size_t* pool_used) {
   if (sv == nullptr) return -1;
-  int run = 0;
-  for (auto& b : sv->batches) run += b.busy ? (int)b.members.size() : 0;
+  int run = sv->ring.in_flight;
   for (auto& l : sv->larges) run += l->busy ? 1 : 0;
   if (queued) *queued = (int)sv->queue.size();
   if (running) *running = run;

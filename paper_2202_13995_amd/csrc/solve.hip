@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kPT) void trsv_persistent_kernel(
       Ld[e >> 7][e & (kTB - 1)] = v[u];
     }
   }
+  for (int e = tid; e < kTB * kRhsChunk; e += kPT) xs[e >> 3][e & 7] = T(0);
   T acc[kRhsChunk];
 #pragma unroll
   for (int c = 0; c < kRhsChunk; ++c)
@@ -401,14 +402,16 @@ __global__ __launch_bounds__(kPT) void trsv_persistent_kernel(
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
       int bad = 0;
-      for (int e = tid; e < kTB * kRhsChunk; e += kPT) {
-        const int k = e >> 3, c = e & 7;
+      // only the cw right-hand sides of this pass (the other slots stay zero)
+      for (int e = tid; e < kTB * cw; e += kPT) {
+        const int k = e / cw, c = e - k * cw;
+        const int ee = k * kRhsChunk + c;
         if constexpr (WPV == 1) {
-          const unsigned long long w = xload(&rj[e]);
+          const unsigned long long w = xload(&rj[ee]);
           bad |= (unsigned)(w >> 32) != tag;
           xs[k][c] = __builtin_bit_cast(T, (unsigned)w);
         } else {
-          const unsigned long long w0 = xload(&rj[2 * e]), w1 = xload(&rj[2 * e + 1]);
+          const unsigned long long w0 = xload(&rj[2 * ee]), w1 = xload(&rj[2 * ee + 1]);
           bad |= ((unsigned)(w0 >> 32) != tag) | ((unsigned)(w1 >> 32) != tag);
           xs[k][c] = __builtin_bit_cast(
               T, ((unsigned long long)(unsigned)w1 << 32) | (unsigned long long)(unsigned)w0);
@@ -505,17 +508,18 @@ __global__ __launch_bounds__(kPT) void trsv_persistent_kernel(
   // right-hand sides, so readers never wait on them)
   const unsigned tag = (unsigned)(I + 1);
   unsigned long long* ri = rec + (size_t)I * kTB * kRhsChunk * WPV;
-  for (int e = tid; e < kTB * kRhsChunk; e += kPT) {
-    const int k = e >> 3, c = e & 7;
-    const bool ok = k < bs && c < cw;
+  for (int e = tid; e < kTB * cw; e += kPT) {
+    const int k = e / cw, c = e - k * cw;
+    const int ee = k * kRhsChunk + c;
+    const bool ok = k < bs;
     const T v = ok ? red[k][c] : T(0);
     if (ok) B[(long long)(r0 + k) * ldb + c0 + c] = v;
     if constexpr (WPV == 1) {
-      xstore(&ri[e], ((unsigned long long)tag << 32) | __builtin_bit_cast(unsigned, v));
+      xstore(&ri[ee], ((unsigned long long)tag << 32) | __builtin_bit_cast(unsigned, v));
     } else {
       const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-      xstore(&ri[2 * e], ((unsigned long long)tag << 32) | (b & 0xffffffffull));
-      xstore(&ri[2 * e + 1], ((unsigned long long)tag << 32) | (b >> 32));
+      xstore(&ri[2 * ee], ((unsigned long long)tag << 32) | (b & 0xffffffffull));
+      xstore(&ri[2 * ee + 1], ((unsigned long long)tag << 32) | (b >> 32));
     }
   }
 }

@@ -77,6 +77,8 @@ def test_mixed_stream_matches_oracle(lp):
         assert r["status"] == 0 and r["info"] == 0, r
         assert r["scaled_residual"] < 16, r
         assert r["batched"] == (1 if n <= 512 else 0)
+        # the request's own device time is part of its latency
+        assert 0.0 < r["device_ms"] <= r["latency_ms"] + 1e-3, r
         check_against_oracle(A, B, X, seed, n, nrhs, prec)
 
 

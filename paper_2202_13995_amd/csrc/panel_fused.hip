@@ -77,11 +77,12 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     int nopiv) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc acc_t;
-  // row blocks of 16 per load batch in (F): a whole 256-row chunk for binary32
-  // rows held one per thread; 8 where registers are tighter
-  constexpr int kRbb = (RPT == 1 && sizeof(T) == 4) ? 16 : 8;
+  // row blocks of 16 per load batch in (F) (8 for binary64: more were slower)
+  constexpr int kRbb = (sizeof(T) == 8) ? 8 : 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* stage = reinterpret_cast<T*>(smem_raw);  // [LW][kChunk] column-major, one row chunk
+  // [RPT][LW][kChunk]: one row chunk column-major while loading and writing
+  // the leaf, all of the workgroup's rows during (F)
+  T* stage = reinterpret_cast<T*>(smem_raw);
   __shared__ T lblk[kLW * (kLW + 1)];         // the leaf's own rows (diagonal block), row-major
   __shared__ double red_key[2][4];
   __shared__ int red_idx[2][4];
@@ -507,22 +508,23 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
       return;
     }
 
-    // (F) own rows below the leaf: A(r, right) -= L(r, leaf) * U(leaf, right),
-    // one 256-row chunk at a time with the chunk's L values staged in LDS
+    // (F) own rows below the leaf: A(r, right) -= L(r, leaf) * U(leaf, right).
+    // The L values of all the workgroup's rows go to LDS first, so the leaf's
+    // registers are free and each wave keeps kRbb row blocks of loads in
+    // flight over the whole row range; every row block of one 16-column block
+    // reuses the U values loaded once.
     const int r_first = max(right0 - base, 0);
-    const int gq = lane >> 4;
-    const int l16 = lane & 15;
-    const int ncb = (nright + 15) >> 4;
+    if (r_first < nrows) {  // the same for the whole workgroup
+      const int gq = lane >> 4;
+      const int l16 = lane & 15;
+      const int ncb = (nright + 15) >> 4;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r0 = kChunk * q;
-      const int lo = max(r_first, r0), hi = min(nrows, r0 + kChunk);
-      if (lo >= hi) continue;  // the same for the whole workgroup
+      for (int q = 0; q < RPT; ++q)
 #pragma unroll
-      for (int c = 0; c < LW; ++c) stage[c * kChunk + tid] = x[q][c];
+        for (int c = 0; c < LW; ++c) stage[(q * LW + c) * kChunk + tid] = x[q][c];
       __syncthreads();
-      const int rb0 = (lo - r0) & ~15;  // chunk-relative
-      const int nrb = (hi - r0 - rb0 + 15) >> 4;
+      const int rb0 = r_first & ~15;
+      const int nrb = (nrows - rb0 + 15) >> 4;
       for (int cbk = wave; cbk < ncb; cbk += 4) {
         const int col = right0 + 16 * cbk + l16;
         const bool colok = col < c0 + W;
@@ -542,11 +544,11 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           acc_t acc[kRbb];
 #pragma unroll
           for (int u = 0; u < kRbb; ++u) {
-            const int rloc = r0 + rb0 + 16 * (rg + u);
+            const int rloc = rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = rloc + MF::drow(gq, v);
-              const bool ok = (rg + u < nrb) && row >= lo && row < hi && colok;
+              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
               const T raw =
                   xload(&A[ok ? (long long)(base + row) * lda + col : (long long)base * lda + c0]);
               acc[u][v] = ok ? -raw : T(0);
@@ -555,17 +557,18 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
 #pragma unroll
           for (int u = 0; u < kRbb; ++u) {
             if (rg + u >= nrb) continue;
-            const int arow = rb0 + 16 * (rg + u) + l16;  // chunk-relative
-            const bool rowok = arow < kChunk;
-            // the row block's L values first, then its products
+            // the row block's L values first (rows past nrows hold zeros),
+            // then its products
+            const int arow = rb0 + 16 * (rg + u) + l16;  // < RPT * kChunk
+            const int sq = arow >> 8, sr = arow & (kChunk - 1);
             T av[LW / 16][4];
 #pragma unroll
             for (int s2 = 0; s2 < LW / 16; ++s2)
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const int k = 16 * s2 + MF::kidx(gq, t);
-                const bool ok = rowok && k < wb;
-                const T a0 = stage[ok ? k * kChunk + arow : 0];
+                const bool ok = k < wb;
+                const T a0 = stage[ok ? (sq * LW + k) * kChunk + sr : 0];
                 av[s2][t] = ok ? a0 : T(0);
               }
 #pragma unroll
@@ -575,11 +578,11 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
           }
 #pragma unroll
           for (int u = 0; u < kRbb; ++u) {
-            const int rloc = r0 + rb0 + 16 * (rg + u);
+            const int rloc = rb0 + 16 * (rg + u);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = rloc + MF::drow(gq, v);
-              const bool ok = (rg + u < nrb) && row >= lo && row < hi && colok;
+              const bool ok = (rg + u < nrb) && row >= r_first && row < nrows && colok;
               if (ok) xstore(&A[(long long)(base + row) * lda + col], -acc[u][v]);
             }
           }
@@ -624,10 +627,10 @@ int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv,
     G = (int)cdiv(rows, R);
   }
   if (R > kPanelRowsPerWg || G > ncu || G > kMaxG || W > 1024) return LP_ENOTSUP;
-  const size_t lds = sizeof(T) * (size_t)kChunk * kLW;
   // 1024 binary64 rows per workgroup keep 16-wide leaves in registers
 #define LP_PANEL_LAUNCH(RPTV, LWV)                                                               \
-  hipLaunchKernelGGL((panel_fused_kernel<T, RPTV, LWV>), dim3(G), dim3(256), lds, s, m, c0, W, A, \
+  hipLaunchKernelGGL((panel_fused_kernel<T, RPTV, LWV>), dim3(G), dim3(256),                     \
+                     sizeof(T) * (size_t)kChunk * (LWV) * (RPTV), s, m, c0, W, A,                \
                      lda,                                                                        \
                      ipiv, info, R, G, (char*)slots, barrier, (T*)staging,                       \
                      (unsigned long long*)keys, (unsigned long long*)keys_next, nopiv ? 1 : 0)

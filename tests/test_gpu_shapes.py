@@ -71,9 +71,13 @@ def planted_panel(seed, m, w):
 # (rows, width, precision, workgroup cap): the shapes lu_factor launches beside
 # the trailing update at n = 32768 / nb = 256 (binary64: 48 workgroups of 704
 # rows) and n = 65536 / nb = 512 (binary64: 64 of 1024 rows; binary32: 128 of
-# 512 rows), plus a binary32 panel of 256 rows per workgroup
+# 512 rows), a binary32 panel of 256 rows per workgroup, binary64 panels of
+# 256 and 512 rows per workgroup with 32-wide leaves, and whole-device panels
+# (cap 0: one workgroup per 256 rows, 254 workgroups here).
 SHAPES = [(32512, 256, "fp64", 48), (65024, 512, "fp64", 64),
-          (65024, 512, "fp32", 128), (32000, 512, "fp32", 128)]
+          (65024, 512, "fp32", 128), (32000, 512, "fp32", 128),
+          (12288, 512, "fp64", 48), (24000, 256, "fp64", 48),
+          (65024, 512, "fp64", 0), (65024, 256, "fp32", 0)]
 
 
 @pytest.mark.parametrize("m,w,prec,wgs", SHAPES)

@@ -489,7 +489,7 @@ def main() -> int:
     ap.add_argument("--serve-lowp", default="fp32", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--serve-small-n", type=int, default=128,
                     help="requests up to this n run in the persistent batched kernel")
-    ap.add_argument("--serve-large-slots", type=int, default=8)
+    ap.add_argument("--serve-large-slots", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ptrans-n", type=int, default=32768)

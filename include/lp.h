@@ -237,6 +237,10 @@ typedef struct {
                            refinement (binary64 fallback)                             */
   double gmres_tol;     /* stop a correction when the preconditioned residual norm has
                            fallen by this factor (default 1e-10)                        */
+  int no_lookahead;     /* 0 (default): the factorizations use look-ahead as lu_factor;
+                           1: they run strictly in order on `stream` with no internal
+                           streams (what a server running several solves at once wants:
+                           fewer streams than hardware queues)                        */
 } lp_ir_opts;
 
 /* Bytes of device workspace lu_solve_ir needs. */
@@ -296,7 +300,10 @@ int lp_ir_decide(const double *h, int len, int corrections, int max_iter);
  * request, each request completing on its own (for those the low-precision
  * route factors in binary32).  The kernel exits after 2 ms without requests
  * and is launched again when one arrives.  Larger requests run the blocked
- * path on their own stream (large_slots at once).  A result depends only on
+ * path on a worker thread and a stream of their own (large_slots at once;
+ * 4 is a good value), their factorizations without look-ahead (no internal
+ * streams: with several solves in flight the streams would outnumber the
+ * hardware queues and wait behind each other).  A result depends only on
  * the request (size, precision, data), never on what else was in flight.
  * Not thread-safe: one thread drives a server.  The caller keeps A, B and X
  * (device memory) alive until the request's ticket is returned by

@@ -49,7 +49,7 @@ class IRReport(ctypes.Structure):
 class IROpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("gmres", ctypes.c_int),
                 ("gmres_restart", ctypes.c_int), ("gmres_max_inner", ctypes.c_int),
-                ("gmres_tol", ctypes.c_double)]
+                ("gmres_tol", ctypes.c_double), ("no_lookahead", ctypes.c_int)]
 
 
 class FactorOpts(ctypes.Structure):
@@ -295,7 +295,7 @@ def residual_check(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out=None,
 
 def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: int = 30,
              X=None, work=None, stream=None, gmres: int = 1, gmres_restart: int = 64,
-             gmres_max_inner: int = 64, gmres_tol: float = 1e-10):
+             gmres_max_inner: int = 64, gmres_tol: float = 1e-10, lookahead: bool = True):
     """Mixed-precision solve with binary64 iterative refinement. Returns (X, report).
     gmres: 0 classical corrections only, 1 switch to GMRES corrections when
     classical ones stall (default), 2 GMRES only (lu_solve_ir_ex)."""
@@ -312,7 +312,8 @@ def solve_ir(A: torch.Tensor, B: torch.Tensor, nb: int, prec="bf16", max_iter: i
             raise ValueError("unsupported solve_ir arguments")
         work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     rep = IRReport()
-    opts = IROpts(max_iter, gmres, gmres_restart, gmres_max_inner, gmres_tol)
+    opts = IROpts(max_iter, gmres, gmres_restart, gmres_max_inner, gmres_tol,
+                  0 if lookahead else 1)
     _check("lu_solve_ir", _lib().lu_solve_ir_ex(n, nb, p, A.data_ptr(), lda, B.data_ptr(), ldb,
                                                 X.data_ptr(), ldx, nrhs, ctypes.byref(opts),
                                                 work.data_ptr(), work.numel(), ctypes.byref(rep),

@@ -252,6 +252,7 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
   o.gmres_restart = 64;
   o.gmres_max_inner = 64;
   o.gmres_tol = 1e-10;
+  o.no_lookahead = 0;
   if (opts != nullptr) o = *opts;
   if (n < 0) return -1;
   if (nb < 1) return -2;
@@ -264,7 +265,8 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
   if (ldx < std::max(1, nrhs)) return -9;
   if (nrhs < 0) return -10;
   if (o.max_iter < 0 || o.max_iter > 62 || o.gmres < 0 || o.gmres > 2 || o.gmres_restart < 1 ||
-      o.gmres_restart > kMaxRestart || o.gmres_max_inner < 1 || !(o.gmres_tol > 0.0))
+      o.gmres_restart > kMaxRestart || o.gmres_max_inner < 1 || !(o.gmres_tol > 0.0) ||
+      o.no_lookahead < 0 || o.no_lookahead > 1)
     return -11;
   if (work == nullptr) return -12;
   if (rep == nullptr) return -14;
@@ -278,6 +280,11 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
     return LP_OK;
   }
   const int max_iter = o.max_iter;
+  lp_factor_opts fo;
+  fo.lookahead = o.no_lookahead ? 0 : 1;
+  fo.panel_cus = 0;
+  fo.panel_rows = 0;
+  fo.no_pivoting = 0;
   const IRLayout L = ir_layout(n, nb, prec, nrhs);
   char* w = (char*)work;
   int32_t* ipiv = (int32_t*)(w + L.ipiv);
@@ -320,8 +327,8 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
     hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks_for(nn * nn)), dim3(256), 0, s, n, n, A, lda,
                        A64, nn);
     LP_LAUNCH_CHECK();
-    int r = lu_factor(n, nb, LP_FP64, A64, n, ipiv, info, w + L.fwork,
-                      lu_workspace_bytes(n, nb, LP_FP64), s);
+    int r = lu_factor_ex(n, nb, LP_FP64, A64, n, ipiv, info, w + L.fwork,
+                         lu_workspace_bytes(n, nb, LP_FP64), &fo, nullptr, s);
     if (r != LP_OK) return r;
     hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks_for(nn * nrhs)), dim3(256), 0, s, n, nrhs, B,
                        ldb, X, ldx);
@@ -456,8 +463,8 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
     float* A32w = (float*)(w + L.big);
     if ((rc = launch_convert(1, n, n, A, lda, A32w, nn, s)) != LP_OK) return rc;
     if ((rc = evs.record(s, &e_conv)) != LP_OK) return rc;
-    if ((rc = lu_factor(n, nb, prec, A32w, n, ipiv, info, w + L.fwork,
-                        lu_workspace_bytes(n, nb, prec), s)) != LP_OK)
+    if ((rc = lu_factor_ex(n, nb, prec, A32w, n, ipiv, info, w + L.fwork,
+                           lu_workspace_bytes(n, nb, prec), &fo, nullptr, s)) != LP_OK)
       return rc;
     if ((rc = evs.record(s, &e_fact)) != LP_OK) return rc;
     if ((rc = launch_convert(1, n, nrhs, B, ldb, D, nrhs, s)) != LP_OK) return rc;
@@ -566,6 +573,7 @@ int lu_solve_ir(int n, int nb, int prec, const double* A, int lda, const double*
   o.gmres_restart = 64;
   o.gmres_max_inner = 64;
   o.gmres_tol = 1e-10;
+  o.no_lookahead = 0;
   if (max_iter < 0 || max_iter > 62) return -11;
   return lu_solve_ir_ex(n, nb, prec, A, lda, B, ldb, X, ldx, nrhs, &o, work, work_bytes, rep,
                         stream);

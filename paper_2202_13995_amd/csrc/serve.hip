@@ -743,7 +743,10 @@ static int retire(lp_server* sv) {
 // slot's stream (it issues many launches, and the refinement takes host
 // decisions), so the poll loop keeps admitting and publishing other work.  A
 // failure is reported as a failed request (status 1), never stranded; the
-// request's memory returns to the pool at retirement either way.
+// request's memory returns to the pool at retirement either way.  The
+// factorizations run without look-ahead: its two internal streams per solve
+// would multiply the streams sharing the device's few hardware queues, where
+// a kernel at the head of a queue holds up every stream behind it.
 static void run_large_fp64(lp_server::Large* l, const lp_request r, char* base,
                            hipEvent_t ready) {
   hipStream_t s = l->s;
@@ -773,7 +776,13 @@ static void run_large_fp64(lp_server::Large* l, const lp_request r, char* base,
   if (rc == LP_OK)
     hip(hipMemcpy2DAsync(r.X, sizeof(double) * r.ldx, r.B, sizeof(double) * r.ldb,
                          sizeof(double) * r.nrhs, r.n, hipMemcpyDeviceToDevice, s));
-  if (rc == LP_OK) rc = lu_factor(r.n, r.nb, LP_FP64, F, r.n, ipiv, info, fw, fwb, s);
+  lp_factor_opts fo;
+  fo.lookahead = 0;  // no internal streams (see above)
+  fo.panel_cus = 0;
+  fo.panel_rows = 0;
+  fo.no_pivoting = 0;
+  if (rc == LP_OK)
+    rc = lu_factor_ex(r.n, r.nb, LP_FP64, F, r.n, ipiv, info, fw, fwb, &fo, nullptr, s);
   if (rc == LP_OK)
     rc = lu_solve_ex(r.n, LP_FP64, F, r.n, ipiv, info, r.X, r.ldx, r.nrhs, nullptr, sw, swb, s);
   if (rc == LP_OK) rc = residual_check(r.n, r.A, r.lda, r.X, r.ldx, r.B, r.ldb, r.nrhs, out, s);
@@ -804,10 +813,17 @@ static int launch_large(lp_server* sv, lp_server::Large& l, const lp_server::Pen
     if (r.prec == LP_FP64) {
       run_large_fp64(lpt, r, base, ready);
     } else {
+      lp_ir_opts o;
+      o.max_iter = maxit;
+      o.gmres = 1;
+      o.gmres_restart = 64;
+      o.gmres_max_inner = 64;
+      o.gmres_tol = 1e-10;
+      o.no_lookahead = 1;  // no internal streams (see run_large_fp64)
       int rc = LP_EHIP_BASE;
       if (hipStreamWaitEvent(lpt->s, ready, 0) == hipSuccess)
-        rc = lu_solve_ir(r.n, r.nb, r.prec, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, r.nrhs, maxit,
-                         base, wsb, &lpt->rep, lpt->s);
+        rc = lu_solve_ir_ex(r.n, r.nb, r.prec, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, r.nrhs, &o,
+                            base, wsb, &lpt->rep, lpt->s);
       lpt->rc = rc;
     }
     lpt->finished.store(1, std::memory_order_release);

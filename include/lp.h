@@ -123,6 +123,11 @@ typedef struct {
                      0 (default): min(1024 * panel_cus, 3 n / 4) */
   int no_pivoting;  /* 0 (default): partial pivoting; 1: no row exchanges, as
                        lu_factor_nopiv (panel_cus / panel_rows are then unused) */
+  int panel_split_rows; /* with partial pivoting, panels of 256 columns or more and
+                           at least this many rows are factored in two halves, the
+                           right half updated by one product on the GEMM kernel
+                           between them: 0 (default) a per-precision choice, -1 never,
+                           k > 0 from k rows */
 } lp_factor_opts;
 
 typedef struct {

@@ -54,7 +54,8 @@ class IROpts(ctypes.Structure):
 
 class FactorOpts(ctypes.Structure):
     _fields_ = [("lookahead", ctypes.c_int), ("panel_cus", ctypes.c_int),
-                ("panel_rows", ctypes.c_int), ("no_pivoting", ctypes.c_int)]
+                ("panel_rows", ctypes.c_int), ("no_pivoting", ctypes.c_int),
+                ("panel_split_rows", ctypes.c_int)]
 
 
 class FactorProfile(ctypes.Structure):
@@ -217,12 +218,15 @@ def workspace(n: int, nb: int, prec="fp64", device="cuda") -> torch.Tensor:
 
 def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=None,
               stream=None, lookahead: bool = True, profile: bool = False,
-              panel_cus: int = 0, panel_rows: int = 0, pivot: bool = True):
+              panel_cus: int = 0, panel_rows: int = 0, pivot: bool = True,
+              split_rows: int = 0):
     """In place: A := L\\U. Returns (ipiv int32[n], info int32[1]) on the device, plus a
     per-phase profile dict when profile=True (the call then synchronizes).
     panel_cus / panel_rows: compute units reserved for short panels (see
     lp_factor_opts in include/lp.h; 0 / 0: never).  pivot=False: the no-pivot
-    elimination of lu_factor_nopiv (ipiv is then the identity)."""
+    elimination of lu_factor_nopiv (ipiv is then the identity).  split_rows: panels of at
+    least this many rows in two halves (lp_factor_opts.panel_split_rows; 0 the default
+    choice, -1 never)."""
     p = _prec(prec)
     lda = _mat(A, storage_dtype(p), "A")
     n = A.shape[0]
@@ -234,7 +238,8 @@ def lu_factor(A: torch.Tensor, nb: int, prec="fp64", work=None, ipiv=None, info=
         ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
-    opts = FactorOpts(1 if lookahead else 0, panel_cus, panel_rows, 0 if pivot else 1)
+    opts = FactorOpts(1 if lookahead else 0, panel_cus, panel_rows, 0 if pivot else 1,
+                      split_rows)
     prof = FactorProfile() if profile else None
     _check("lu_factor", _lib().lu_factor_ex(n, nb, p, A.data_ptr(), lda, ipiv.data_ptr(),
                                          info.data_ptr(), work.data_ptr(), work.numel(),

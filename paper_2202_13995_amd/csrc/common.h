@@ -88,10 +88,13 @@ size_t panel_staging_bytes(int W);
 // j); only for at most 1024 rows (one workgroup), else LP_ENOTSUP.
 size_t panel_keys_bytes();
 constexpr int kPanelRowsPerWg = 1024;
+// next_w: the widest later launch that uses keys_next (its key slots are
+// cleared by this launch); the launch's own width when 0.
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s, int max_wgs = 0, bool nopiv = false);
+                       void* keys_next, hipStream_t s, int max_wgs = 0, bool nopiv = false,
+                       int next_w = 0);
 
 // X U = B for X, U upper triangular (non-unit) w x w, B m x w (ld ldb), in
 // place: B := B U^-1 (the "left blocks" of the no-pivot LU).  work:

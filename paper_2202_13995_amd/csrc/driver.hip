@@ -60,7 +60,7 @@ constexpr int kPlanRing = 4;
 
 struct FactorLayout {
   size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, plan_bytes, linv_trail,
-      linv_left, pack_a, pack_b, total;
+      linv_left, plan_panel, linv_panel, pack_a, pack_b, total;
 };
 
 bool packs_operands(int prec) { return prec == LP_BF16 || prec == LP_FP16; }
@@ -87,6 +87,11 @@ FactorLayout factor_layout(int n, int nb, int prec) {
   // block inverses of the no-pivot left-block solve (its own stream)
   L.linv_left = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
+  // the exchanges and block inverses inside a split panel (the panel's stream)
+  L.plan_panel = off;
+  off += L.plan_bytes;
+  L.linv_panel = off;
+  off = align_up(off + trsm_workspace_bytes(kMaxNb / 2), 256);
   // bfloat16 / half: the packed operands of the trailing update (-L of the
   // step; U^T of a column range, placed at a 256-row offset per range)
   L.pack_a = L.pack_b = 0;
@@ -116,6 +121,7 @@ struct Factor {
   void* staging;
   void* keys[2];  // per-launch key buffers, alternating; the first starts zeroed
   hipStream_t s;
+  int max_w = 0;  // the widest panel launch of the factorization (key slots to clear)
 
   T* at(long long i, long long j) const { return A + i * lda + j; }
 
@@ -125,7 +131,35 @@ struct Factor {
     const int idx = next_barrier++;
     unsigned* bar = barriers + idx;
     return launch_panel_fused<T>(m, j0, w, A, lda, ipiv, info, slots, bar, staging,
-                                 keys[idx & 1], keys[(idx + 1) & 1], s, max_wgs);
+                                 keys[idx & 1], keys[(idx + 1) & 1], s, max_wgs, false, max_w);
+  }
+
+  // The same columns in two halves (partial pivoting, w >= 256): the left
+  // half in one launch; its row exchanges, the "top" solve U12 = L11^-1 A12
+  // and the update A22 -= L21 U12 applied to the right half; the right half
+  // in a second launch; its row exchanges applied to the left half.  Inside
+  // one launch the columns right of each leaf are read and written once per
+  // leaf, so the panel moves about m w^2 / (2 leaf width) elements; the split
+  // moves a quarter of that plus one rank-h product on the GEMM kernel.  The
+  // pivots and the arithmetic of each element are those of partial pivoting;
+  // only the grouping of the right half's updates changes.
+  int panel_split(int j0, int w, int max_wgs, void* plan, void* linv) {
+    const int h = (w / 64) * 32;
+    int rc = panel(j0, h, max_wgs);
+    if (rc != LP_OK) return rc;
+    if ((rc = launch_swap_plan(ipiv, j0, j0 + h, plan, s)) != LP_OK) return rc;
+    if ((rc = launch_swap_apply<T>(A, lda, j0 + h, j0 + w, 0, 0, h, plan, s)) != LP_OK)
+      return rc;
+    if ((rc = launch_trsm_lower_unit<T>(h, w - h, at(j0, j0), lda, at(j0, j0 + h), lda, linv,
+                                        s)) != LP_OK)
+      return rc;
+    const int prec = sizeof(T) == 8 ? LP_FP64 : LP_FP32;
+    if ((rc = launch_gemm_update(prec, m - j0 - h, w - h, h, at(j0 + h, j0), lda, at(j0, j0 + h),
+                                 lda, at(j0 + h, j0 + h), lda, s, kGemmPanel)) != LP_OK)
+      return rc;
+    if ((rc = panel(j0 + h, w - h, max_wgs)) != LP_OK) return rc;
+    if ((rc = launch_swap_plan(ipiv, j0 + h, j0 + w, plan, s)) != LP_OK) return rc;
+    return launch_swap_apply<T>(A, lda, j0, j0 + h, 0, 0, w - h, plan, s);
   }
 
   // the same columns without pivoting, as the paper's LU and left kernels:
@@ -302,6 +336,7 @@ struct FactorCfg {
   int panel_cus = 0;
   int panel_rows = 0;
   bool pivot = true;  // false: the paper's elimination without row exchanges
+  int split_rows = 0;  // panels of 256 columns or more and this many rows in two halves
 };
 
 // Streams restricted by compute-unit masks: the first `reserve` mask bits for
@@ -339,6 +374,19 @@ int lookahead_panel_wgs(int rows) {
   return std::max(sizeof(T) == 8 ? 48 : 128, (int)cdiv(rows, kPanelRowsPerWg));
 }
 
+// Rows from which a panel is split in two halves by default (-1: never).
+// Measured on one MI355X at n = 65536, nb = 512: binary32 panels of the
+// low-precision factorization, where the panel is the longer chain, gain from
+// the split at every size (bfloat16 factorization 832 -> 800 ms); binary64
+// panels lose at every threshold (3.17 s unsplit, 3.30 s splitting only panels
+// of 49152 rows or more, 3.48 s splitting all; n = 32768, nb = 256: 0.55
+// against 0.64 s): beside the binary64 update the extra launches on the
+// panel's stream wait for compute units and lengthen its chain.
+template <typename T>
+int default_split_rows() {
+  return sizeof(T) == 8 ? -1 : 1;
+}
+
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
                 char* work, hipStream_t s, const FactorCfg& cfg, Prof& prof) {
@@ -352,11 +400,16 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     return rc;
   Factor<T> f{n, A, lda, ipiv, info, work + L.slots, (unsigned*)(work + L.barriers),
               (int)L.n_barriers, 0, work + L.staging, {work + L.keys0, work + L.keys1}, s};
+  f.max_w = std::min(nb, n);  // a split panel's halves are narrower, its right half may be wider
   void* linv_trail = work + L.linv_trail;
   void* linv_left = work + L.linv_left;
   const bool piv = cfg.pivot;
+  const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows<T>();
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
-    return piv ? f.panel(j0, w, max_wgs) : f.panel_nopiv(j0, w, linv_left);
+    if (!piv) return f.panel_nopiv(j0, w, linv_left);
+    if (split_rows > 0 && w >= 256 && n - j0 >= split_rows && n - j0 > kPanelRowsPerWg)
+      return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel);
+    return f.panel(j0, w, max_wgs);
   };
   char* plan_ring = work + L.plan_trail;
   void* plan_trail = plan_ring;  // the current step's plan
@@ -624,6 +677,7 @@ int lu_factor_ex(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, int32
     cfg.panel_cus = opts->panel_cus;
     cfg.panel_rows = opts->panel_rows;
     cfg.pivot = opts->no_pivoting == 0;
+    cfg.split_rows = opts->panel_split_rows;
   }
   hipStream_t s = (hipStream_t)stream;
   if (prec == LP_FP64)
@@ -670,6 +724,7 @@ int lu_factor_nopiv(int n, int nb, int prec, void* A, int lda, int32_t* ipiv, in
   o.panel_cus = 0;
   o.panel_rows = 0;
   o.no_pivoting = 1;
+  o.panel_split_rows = 0;
   return lu_factor_ex(n, nb, prec, A, lda, ipiv, info, work, work_bytes, &o, nullptr, stream);
 }
 

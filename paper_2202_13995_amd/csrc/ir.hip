@@ -285,6 +285,7 @@ int lu_solve_ir_ex(int n, int nb, int prec, const double* A, int lda, const doub
   fo.panel_cus = 0;
   fo.panel_rows = 0;
   fo.no_pivoting = 0;
+  fo.panel_split_rows = 0;
   const IRLayout L = ir_layout(n, nb, prec, nrhs);
   char* w = (char*)work;
   int32_t* ipiv = (int32_t*)(w + L.ipiv);

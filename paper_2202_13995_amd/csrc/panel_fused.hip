@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
     int32_t* __restrict__ info, int R, int G, char* __restrict__ slots,
     unsigned* __restrict__ barrier, T* __restrict__ staging,
     unsigned long long* __restrict__ keys, unsigned long long* __restrict__ keys_next,
-    int nopiv) {
+    int nopiv, int CW) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc acc_t;
   // row blocks of 16 per load batch in (F) (8 for binary64: more were slower)
@@ -116,11 +116,11 @@ __global__ __launch_bounds__(256, (RPT == 1) ? 2 : 1) void panel_fused_kernel(
   unsigned nbar = 0;
   // the first zero pivot so far (read once; only this launch writes it meanwhile)
   int info_val = (g == 0 && tid == 0) ? *info : 0;
-  // the next panel launch has at most W columns; it may have more workgroups
-  // than this one, so every key slot of those columns is cleared
+  // the next panel launch has at most CW columns; it may have more
+  // workgroups than this one, so every key slot of those columns is cleared
   if (G > 1) {  // a single-workgroup launch is followed by single-workgroup launches
-    for (int e = g * blockDim.x + tid; e < W * kMaxG; e += G * blockDim.x)
-      xstore(&keys_next[(size_t)(e / W) * kKeyStride + e % W], 0ull);
+    for (int e = g * blockDim.x + tid; e < CW * kMaxG; e += G * blockDim.x)
+      xstore(&keys_next[(size_t)(e / CW) * kKeyStride + e % CW], 0ull);
   }
   // the panel is the critical path while the trailing update runs beside it
   // on the same compute units: its waves issue first
@@ -602,8 +602,9 @@ size_t panel_keys_bytes() { return sizeof(unsigned long long) * (size_t)kKeySlot
 template <typename T>
 int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv, int32_t* info,
                        void* slots, unsigned* barrier, void* staging, void* keys,
-                       void* keys_next, hipStream_t s, int max_wgs, bool nopiv) {
+                       void* keys_next, hipStream_t s, int max_wgs, bool nopiv, int next_w) {
   const int rows = m - c0;
+  const int CW = std::max(W, next_w);
   if (rows <= 0 || W <= 0) return LP_OK;
   if (W > rows) return LP_ENOTSUP;
   if (nopiv && rows > kPanelRowsPerWg) return LP_ENOTSUP;  // one workgroup only
@@ -626,14 +627,15 @@ int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv,
     if (R < kChunk) R = kChunk;
     G = (int)cdiv(rows, R);
   }
-  if (R > kPanelRowsPerWg || G > ncu || G > kMaxG || W > 1024) return LP_ENOTSUP;
+  if (R > kPanelRowsPerWg || G > ncu || G > kMaxG || CW > 1024) return LP_ENOTSUP;
   // 1024 binary64 rows per workgroup keep 16-wide leaves in registers
 #define LP_PANEL_LAUNCH(RPTV, LWV)                                                               \
   hipLaunchKernelGGL((panel_fused_kernel<T, RPTV, LWV>), dim3(G), dim3(256),                     \
                      sizeof(T) * (size_t)kChunk * (LWV) * (RPTV), s, m, c0, W, A,                \
                      lda,                                                                        \
                      ipiv, info, R, G, (char*)slots, barrier, (T*)staging,                       \
-                     (unsigned long long*)keys, (unsigned long long*)keys_next, nopiv ? 1 : 0)
+                     (unsigned long long*)keys, (unsigned long long*)keys_next, nopiv ? 1 : 0,  \
+                     CW)
   if (R <= kChunk)
     LP_PANEL_LAUNCH(1, 32);
   else if (R <= 2 * kChunk)
@@ -649,9 +651,9 @@ int launch_panel_fused(int m, int c0, int W, T* A, long long lda, int32_t* ipiv,
 
 template int launch_panel_fused<double>(int, int, int, double*, long long, int32_t*, int32_t*,
                                         void*, unsigned*, void*, void*, void*, hipStream_t, int,
-                                        bool);
+                                        bool, int);
 template int launch_panel_fused<float>(int, int, int, float*, long long, int32_t*, int32_t*,
                                        void*, unsigned*, void*, void*, void*, hipStream_t, int,
-                                       bool);
+                                       bool, int);
 
 }  // namespace lp

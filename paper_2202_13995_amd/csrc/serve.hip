@@ -781,6 +781,7 @@ static void run_large_fp64(lp_server::Large* l, const lp_request r, char* base,
   fo.panel_cus = 0;
   fo.panel_rows = 0;
   fo.no_pivoting = 0;
+  fo.panel_split_rows = 0;
   if (rc == LP_OK)
     rc = lu_factor_ex(r.n, r.nb, LP_FP64, F, r.n, ipiv, info, fw, fwb, &fo, nullptr, s);
   if (rc == LP_OK)

@@ -253,3 +253,29 @@ def test_classical_only_mode(lp):
     r = rep.as_dict()
     assert r["gmres_corrections"] == 0 and r["gmres_steps"] == 0
     assert r["scaled_residual"] < 16
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_refinement_without_lookahead(lp, prec):
+    """lp_ir_opts.no_lookahead runs the factorization's steps in order on one
+    stream.  In binary32 every element sees the same operations in the same
+    order, so x, the history and the decisions are bitwise the same; with
+    bfloat16 operands the next panel's columns may take the unpacked update
+    kernel under look-ahead, so there both must converge to the same x within
+    the refinement's accuracy."""
+    n, nb = 1536, 128
+    A = inputs.matrix(91, n, shift=float(n))
+    B = inputs.rhs(91, n, 2)
+    out = []
+    for la in (True, False):
+        X, rep = lp.solve_ir(cuda(A), cuda(B), nb, prec, lookahead=la)
+        r = rep.as_dict()
+        out.append((host(X), r["history"], r["iterations"], r["fell_back"]))
+    for x, hist, _, fb in out:
+        assert hist[-1] < 16 and fb == 0
+    if prec == "fp32":
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1:] == out[1][1:]
+    else:
+        d = np.max(np.abs(out[0][0] - out[1][0])) / np.max(np.abs(out[1][0]))
+        assert d <= 1e-10, d

@@ -181,14 +181,15 @@ def traffic_from_profile(kernel_src: str, n: int, nb: int):
 
 
 def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_leg=True,
-                x_ref=None, x_ref_label=None, nopiv_leg=False):
+                x_ref=None, x_ref_label=None, nopiv_leg=False, fp64_nb=None):
     """R timed solves (after one untimed) of one system through the
     low-precision factorization plus binary64 refinement (and the binary64
     fallback when refinement fails).  With fp64_leg the binary64 blocked path
     is timed on that same system the same way, for the speedup (and with
     nopiv_leg the binary64 path without row exchanges too).  The forward
     error is taken against x_ref (the oracle's or the binary64 path's x) and
-    the backward error is the scaled residual."""
+    the backward error is the scaled residual.  The binary64 legs use block
+    fp64_nb (default nb): each path at its own best block size."""
     A = torch.empty((n, n), dtype=torch.float64, device=dev)
     inputs.fill_matrix_(A, seed, shift=shift)
     B = torch.empty((n, nrhs), dtype=torch.float64, device=dev)
@@ -234,7 +235,8 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
     if fp64_leg:
         A64 = torch.empty_like(A)
         X64 = torch.empty_like(B)
-        w64 = lp.workspace(n, nb, "fp64", dev)
+        nb64 = fp64_nb or nb
+        w64 = lp.workspace(n, nb64, "fp64", dev)
         sw64 = torch.empty(lp.lib.lu_solve_workspace_bytes(n, lp.FP64, nrhs), dtype=torch.uint8,
                            device=dev)
         ipiv = torch.empty(n, dtype=torch.int32, device=dev)
@@ -246,14 +248,15 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
             X64.copy_(B)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            lp.lu_factor(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
+            lp.lu_factor(A64, nb64, "fp64", work=w64, ipiv=ipiv, info=info)
             lp.lu_solve(A64, ipiv, info, X64, work=sw64)
             out = lp.residual_check(A, X64, B)
             torch.cuda.synchronize()
             if r > 0:  # the first solve is the untimed warm-up
                 t64.append(time.perf_counter() - t0)
         st64 = stats_ms(t64)
-        res["fp64_same_system"] = dict(st64, scaled_residual=float(out[:, 0].max().item()))
+        res["fp64_same_system"] = dict(st64, scaled_residual=float(out[:, 0].max().item()),
+                                       nb=nb64)
         res["fp64_ms_same_system"] = st64["median_ms"]
         res["speedup_vs_fp64"] = st64["median_ms"] / st["median_ms"]
         res["forward_error_vs_fp64_path"] = forward_error(X, X64)
@@ -267,7 +270,7 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
                 X64.copy_(B)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                lp.lu_factor_nopiv(A64, nb, "fp64", work=w64, ipiv=ipiv, info=info)
+                lp.lu_factor_nopiv(A64, nb64, "fp64", work=w64, ipiv=ipiv, info=info)
                 lp.lu_solve(A64, ipiv, info, X64, work=sw64)
                 out = lp.residual_check(A, X64, B)
                 torch.cuda.synchronize()
@@ -469,7 +472,11 @@ def main() -> int:
     ap.add_argument("--mixed-prec", default="bf16", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--mixed-n", type=int, default=65536,
                     help="order of the mixed-precision system (0: --n)")
-    ap.add_argument("--mixed-nb", type=int, default=512, help="0: --nb")
+    ap.add_argument("--mixed-nb", type=int, default=1024,
+                    help="block of the shifted mixed solve (0: --nb); bfloat16 / half "
+                         "factorizations are fastest with 1024")
+    ap.add_argument("--mixed-unshifted-nb", type=int, default=0,
+                    help="block of the unshifted mixed solves (0: --nb)")
     ap.add_argument("--mixed-reps", type=int, default=3,
                     help="timed solves per mixed-precision leg (after one untimed)")
     ap.add_argument("--no-mixed-unshifted", action="store_true",
@@ -637,10 +644,14 @@ def main() -> int:
         mnb = args.mixed_nb or nb
         log(f"[bench] mixed {args.mixed_prec} n={mn} nb={mnb} shift={mn} ...")
         line["mixed_ir"] = bench_mixed(lp, inputs, torch, dev, mn, mnb, args.mixed_prec,
-                                       float(mn), args.seed, R, args.nrhs, nopiv_leg=True)
+                                       float(mn), args.seed, R, args.nrhs, nopiv_leg=True,
+                                       fp64_nb=nb)
         log(f"[bench] mixed done: {line['mixed_ir']['ms_per_solve']:.1f} ms/solve, "
             f"speedup {line['mixed_ir']['speedup_vs_fp64']:.2f}x")
         if not args.no_mixed_unshifted:
+            # the unshifted variants at the headline's block size: their
+            # binary64 fallback is then the headline's solve
+            mnb = args.mixed_unshifted_nb or nb
             same = mn == n and mnb == nb
             log(f"[bench] mixed {args.mixed_prec} n={mn} unshifted ...")
             line["mixed_ir_unshifted"] = bench_mixed(

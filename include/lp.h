@@ -126,8 +126,9 @@ typedef struct {
   int panel_split_rows; /* with partial pivoting, panels of 256 columns or more and
                            at least this many rows are factored in two halves, the
                            right half updated by one product on the GEMM kernel
-                           between them: 0 (default) a per-precision choice, -1 never,
-                           k > 0 from k rows */
+                           between them: 0 (default) every such panel of the bfloat16
+                           and half factorizations, none in binary64 and binary32;
+                           -1 never; k > 0 from k rows */
 } lp_factor_opts;
 
 typedef struct {

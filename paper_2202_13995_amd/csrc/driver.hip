@@ -143,9 +143,13 @@ struct Factor {
   // moves a quarter of that plus one rank-h product on the GEMM kernel.  The
   // pivots and the arithmetic of each element are those of partial pivoting;
   // only the grouping of the right half's updates changes.
-  int panel_split(int j0, int w, int max_wgs, void* plan, void* linv) {
+  int panel_split(int j0, int w, int max_wgs, void* plan, void* linv, int depth) {
     const int h = (w / 64) * 32;
-    int rc = panel(j0, h, max_wgs);
+    auto half = [&](int c, int ww) -> int {
+      return (depth > 1 && ww >= 256) ? panel_split(c, ww, max_wgs, plan, linv, depth - 1)
+                                      : panel(c, ww, max_wgs);
+    };
+    int rc = half(j0, h);
     if (rc != LP_OK) return rc;
     if ((rc = launch_swap_plan(ipiv, j0, j0 + h, plan, s)) != LP_OK) return rc;
     if ((rc = launch_swap_apply<T>(A, lda, j0 + h, j0 + w, 0, 0, h, plan, s)) != LP_OK)
@@ -157,7 +161,7 @@ struct Factor {
     if ((rc = launch_gemm_update(prec, m - j0 - h, w - h, h, at(j0 + h, j0), lda, at(j0, j0 + h),
                                  lda, at(j0 + h, j0 + h), lda, s, kGemmPanel)) != LP_OK)
       return rc;
-    if ((rc = panel(j0 + h, w - h, max_wgs)) != LP_OK) return rc;
+    if ((rc = half(j0 + h, w - h)) != LP_OK) return rc;
     if ((rc = launch_swap_plan(ipiv, j0 + h, j0 + w, plan, s)) != LP_OK) return rc;
     return launch_swap_apply<T>(A, lda, j0, j0 + h, 0, 0, w - h, plan, s);
   }
@@ -374,18 +378,20 @@ int lookahead_panel_wgs(int rows) {
   return std::max(sizeof(T) == 8 ? 48 : 128, (int)cdiv(rows, kPanelRowsPerWg));
 }
 
-// Rows from which a panel is split in two halves by default (-1: never).
-// Measured on one MI355X at n = 65536, nb = 512: binary32 panels of the
-// low-precision factorization, where the panel is the longer chain, gain from
-// the split at every size (bfloat16 factorization 832 -> 800 ms); binary64
-// panels lose at every threshold (3.17 s unsplit, 3.30 s splitting only panels
-// of 49152 rows or more, 3.48 s splitting all; n = 32768, nb = 256: 0.55
-// against 0.64 s): beside the binary64 update the extra launches on the
-// panel's stream wait for compute units and lengthen its chain.
-template <typename T>
-int default_split_rows() {
-  return sizeof(T) == 8 ? -1 : 1;
-}
+// Panels split in halves by default: those of the bfloat16 / half
+// factorizations (-1: never).  Measured on one MI355X at n = 65536: there the
+// trailing update is bound by memory traffic and the panel is the longer
+// chain, and the split gains at every size (nb = 512: 832 -> 800 ms; nb =
+// 1024: 861 -> 736 ms with halves split again, 770 ms without).  Where the
+// update is bound by the matrix cores the extra launches on the panel's
+// stream wait for compute units and lengthen its chain: binary64 3.17 s
+// unsplit against 3.30 s splitting only panels of 49152 rows or more and 3.48
+// s splitting all (n = 32768, nb = 256: 0.55 against 0.64 s); binary32 2.54
+// against 2.64 s.
+int default_split_rows(int prec) { return packs_operands(prec) ? 1 : -1; }
+// halves of 256 columns or more are split again once (quarters of a 1024
+// panel: 736 ms; a third level 737-749 ms)
+constexpr int kSplitDepth = 2;
 
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
@@ -404,11 +410,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   void* linv_trail = work + L.linv_trail;
   void* linv_left = work + L.linv_left;
   const bool piv = cfg.pivot;
-  const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows<T>();
+  const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows(prec);
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
     if (!piv) return f.panel_nopiv(j0, w, linv_left);
     if (split_rows > 0 && w >= 256 && n - j0 >= split_rows && n - j0 > kPanelRowsPerWg)
-      return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel);
+      return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel,
+                           kSplitDepth);
     return f.panel(j0, w, max_wgs);
   };
   char* plan_ring = work + L.plan_trail;

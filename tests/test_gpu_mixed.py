@@ -279,3 +279,17 @@ def test_refinement_without_lookahead(lp, prec):
     else:
         d = np.max(np.abs(out[0][0] - out[1][0])) / np.max(np.abs(out[1][0]))
         assert d <= 1e-10, d
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_refinement_block_1024(lp, prec):
+    """A 1024-wide block (the bfloat16 benchmark's): each panel is factored in
+    quarters, split twice, with GEMM-kernel updates between them; the refined
+    x must still pass the binary64 scaled-residual check."""
+    n, nb = 4096, 1024
+    A = inputs.matrix(123, n, shift=float(n))
+    B = inputs.rhs(123, n, 2)
+    X, rep = lp.solve_ir(cuda(A), cuda(B), nb, prec)
+    r = rep.as_dict()
+    assert r["converged"] == 1 and r["fell_back"] == 0, r
+    assert np.all(oracle.residual(A, host(X), B)[:, 0] < 16)

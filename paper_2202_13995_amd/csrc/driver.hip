@@ -413,7 +413,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows(prec);
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
     if (!piv) return f.panel_nopiv(j0, w, linv_left);
-    if (split_rows > 0 && w >= 256 && n - j0 >= split_rows && n - j0 > kPanelRowsPerWg)
+    if (split_rows > 0 && w >= 256 && n - j0 >= split_rows)
       return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel,
                            kSplitDepth);
     return f.panel(j0, w, max_wgs);

@@ -205,8 +205,13 @@ def test_gmres_refinement_unshifted(lp, n, nb, nrhs):
     assert r["gmres_corrections"] == r["iterations"] >= 1 and r["gmres_steps"] >= 1
     x_o = oracle.solve(A, B)
     x = host(X)
-    assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
     assert np.all(oracle.residual(A, x, B)[:, 0] < 16)
+    # refinement stops at the benchmark's s < 16, a backward-error criterion:
+    # the forward error is bounded by about kappa * s * n * u, not by 1e-10
+    kappa = np.linalg.cond(A, np.inf)
+    err = np.max(np.abs(x - x_o)) / np.max(np.abs(x_o))
+    print(f"forward error {err:.2e}, kappa_inf {kappa:.2e}")
+    assert err <= 4 * kappa * max(r["scaled_residual"], 1.0) * n * 2.0 ** -53
 
 
 def test_gmres_switch_after_classical_stall(lp):

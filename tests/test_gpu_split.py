@@ -1,11 +1,11 @@
 """GPU parity of the split panel (lp_factor_opts.panel_split_rows; by default
-binary32 panels are split, binary64 panels are not).  With partial pivoting
-(paper, section "High Performance Linpack"), a panel of 256 columns or more
-spread over several workgroups is factored as
-two halves, the right half brought up to date by one product on the GEMM
-kernel between them; only the grouping of the right half's updates changes,
-never a pivot decision rule.  Both forms are compared with the oracle's
-unblocked elimination:
+the panels of the bfloat16 / half factorizations are split, binary64 and
+binary32 panels are not).  With partial pivoting (paper, section "High
+Performance Linpack"), a panel of 256 columns or more is factored as two
+halves, the right half brought up to date by one product on the GEMM kernel
+between them; only the grouping of the right half's updates changes, never a
+pivot decision rule.  Both forms are compared with the oracle's unblocked
+elimination:
 
   * random matrices: pivots bit for bit, x within 1e-10, and every factor
     element within 4 n u (|L||U|)_ij of the oracle's (a bound on any order of
@@ -83,7 +83,7 @@ def planted(seed, n):
 
 
 @pytest.mark.parametrize("split", [True, False])
-@pytest.mark.parametrize("n,nb", [(2304, 256), (2560, 512), (2100, 300)])
+@pytest.mark.parametrize("n,nb", [(2304, 256), (2560, 512), (2100, 300), (1000, 512)])
 def test_split_panels_random_match_oracle(lp, n, nb, split):
     print(f"random n={n} nb={nb} split={split}", flush=True)
     A, B, lu_o, piv_o, info_o, x_o = random_case(n)
@@ -103,7 +103,7 @@ def test_split_panels_random_match_oracle(lp, n, nb, split):
     assert np.max(np.abs(x - x_o)) / np.max(np.abs(x_o)) <= 1e-10
 
 
-@pytest.mark.parametrize("n,nb", [(2048, 512), (2048, 256), (1800, 320)])
+@pytest.mark.parametrize("n,nb", [(2048, 512), (2048, 256), (1800, 320), (1000, 256)])
 def test_split_panels_planted_bit_exact(lp, n, nb):
     print(f"planted n={n} nb={nb}", flush=True)
     P, lu_o, piv_o, info_o = planted_case(11, n)

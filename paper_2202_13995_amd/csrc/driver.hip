@@ -372,7 +372,8 @@ bool make_masked_streams(Lookahead& la, int ncu, int reserve) {
 // is slower than one spread over every compute unit.  Binary32 panels are the
 // longer chain of the low-precision factorization for more of its steps: at
 // most 128 workgroups (512 rows each above 32768 rows) measured best there
-// (n = 65536: 0.94 against 1.00 s with one per 256 rows; 64 everywhere 1.50 s).
+// (n = 65536: 0.94 against 1.00 s with one per 256 rows; 64 everywhere 1.50 s;
+// with split panels at nb = 1024: 64 0.80 s, 96 0.75, 128 0.73, 160-256 0.74-0.76).
 template <typename T>
 int lookahead_panel_wgs(int rows) {
   return std::max(sizeof(T) == 8 ? 48 : 128, (int)cdiv(rows, kPanelRowsPerWg));

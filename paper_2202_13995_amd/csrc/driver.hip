@@ -167,16 +167,39 @@ struct Factor {
   }
 
   // the same columns without pivoting, as the paper's LU and left kernels:
-  // the w x w diagonal block in one workgroup (no pivot search), then the
-  // blocks below it solved against its upper triangle, L21 = A21 U11^-1
-  int panel_nopiv(int j0, int w, void* linv_left) {
-    if (next_barrier >= n_barriers) return LP_ENOTSUP;
-    const int idx = next_barrier++;
-    int rc = launch_panel_fused<T>(j0 + w, j0, w, A, lda, ipiv, info, slots, barriers + idx,
-                                   staging, keys[idx & 1], keys[(idx + 1) & 1], s, 0, true);
+  // the w x w diagonal block in one workgroup (no pivot search; split as
+  // below), then the blocks below it solved against its upper triangle,
+  // L21 = A21 U11^-1
+  int panel_nopiv(int j0, int w, void* linv_left, void* linv_diag, int depth) {
+    int rc = diag_nopiv(j0, j0 + w, w, linv_diag, depth);
     if (rc != LP_OK || j0 + w >= m) return rc;
     return launch_trsm_right_upper<T>(m - j0 - w, w, at(j0, j0), lda, at(j0 + w, j0), lda,
                                       linv_left, s);
+  }
+
+  // LU without pivoting of columns [c, c + w) over rows [c, e) (e - c <= 1024,
+  // one workgroup).  A block of 256 columns or more goes in two halves, split
+  // `depth` times: the left half, then U12 = L11^-1 A12 and A22 -= L21 U12 on
+  // the matrix cores, then the right half -- the same operations the one
+  // launch applies leaf by leaf, a quarter of its in-kernel traffic.
+  int diag_nopiv(int c, int e, int w, void* linv, int depth) {
+    if (depth > 0 && w >= 256) {
+      const int h = (w / 64) * 32;
+      int rc = diag_nopiv(c, e, h, linv, depth - 1);
+      if (rc != LP_OK) return rc;
+      if ((rc = launch_trsm_lower_unit<T>(h, w - h, at(c, c), lda, at(c, c + h), lda, linv, s)) !=
+          LP_OK)
+        return rc;
+      const int prec = sizeof(T) == 8 ? LP_FP64 : LP_FP32;
+      if ((rc = launch_gemm_update(prec, e - c - h, w - h, h, at(c + h, c), lda, at(c, c + h), lda,
+                                   at(c + h, c + h), lda, s, kGemmPanel)) != LP_OK)
+        return rc;
+      return diag_nopiv(c + h, e, w - h, linv, depth - 1);
+    }
+    if (next_barrier >= n_barriers) return LP_ENOTSUP;
+    const int idx = next_barrier++;
+    return launch_panel_fused<T>(e, c, w, A, lda, ipiv, info, slots, barriers + idx, staging,
+                                 keys[idx & 1], keys[(idx + 1) & 1], s, 0, true);
   }
 };
 
@@ -393,6 +416,10 @@ int default_split_rows(int prec) { return packs_operands(prec) ? 1 : -1; }
 // halves of 256 columns or more are split again once (quarters of a 1024
 // panel: 736 ms; a third level 737-749 ms)
 constexpr int kSplitDepth = 2;
+// the no-pivot diagonal block (512 x 512 in one workgroup at nb = 512) in two
+// halves: the n = 65536 no-pivot solve 2.88 -> 2.84 s; halves split again:
+// 3.00 s (more launches waiting for compute units beside the update)
+constexpr int kNopivSplitDepth = 1;
 
 template <typename T>
 int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int32_t* info,
@@ -413,7 +440,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   const bool piv = cfg.pivot;
   const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows(prec);
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
-    if (!piv) return f.panel_nopiv(j0, w, linv_left);
+    if (!piv) return f.panel_nopiv(j0, w, linv_left, work + L.linv_panel, kNopivSplitDepth);
     if (split_rows > 0 && w >= 256 && n - j0 >= split_rows)
       return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel,
                            kSplitDepth);

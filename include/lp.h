@@ -399,8 +399,8 @@ int lp_laswp(int prec, void *A, int lda, int c0, int c1, int k1, int k2,
 /* Triangular solve with a unit lower triangular L (m x m, ld ldl):
  * B := L^-1 B for B m x ncols (ld ldb), in place.  Column-independent.  The
  * blocks to the right of the panel in the paper's "top blocks" update.  work:
- * device scratch of lp_trsm_workspace_bytes(m) bytes (inverses of the 16 x 16
- * diagonal blocks). */
+ * device scratch of lp_trsm_workspace_bytes(m) bytes (inverses of all the
+ * 16 x 16 diagonal blocks, 2 KiB per 16 rows). */
 size_t lp_trsm_workspace_bytes(int m);
 int lp_trsm_lower_unit(int prec, int m, int ncols, const void *L, int ldl, void *B, int ldb,
                        void *work, size_t work_bytes, void *stream);

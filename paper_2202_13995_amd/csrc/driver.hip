@@ -83,7 +83,7 @@ FactorLayout factor_layout(int n, int nb, int prec) {
   L.plan_bytes = align_up(swap_plan_bytes(kMaxNb), 256);
   off += kPlanRing * L.plan_bytes;
   L.linv_trail = off;
-  off = align_up(off + trsm_workspace_bytes(256), 256);
+  off = align_up(off + trsm_workspace_bytes(kMaxNb), 256);
   // block inverses of the no-pivot left-block solve (its own stream)
   L.linv_left = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
@@ -883,7 +883,7 @@ int lp_laswp(int prec, void* A, int lda, int c0, int c1, int k1, int k2, const i
 
 size_t lp_trsm_workspace_bytes(int m) {
   if (m < 0) return 0;
-  return trsm_workspace_bytes(std::min(std::max(m, 1), 256));
+  return trsm_workspace_bytes(std::max(m, 1));  // the inverses of all diagonal blocks
 }
 
 int lp_trsm_lower_unit(int prec, int m, int ncols, const void* L, int ldl, void* B, int ldb,

@@ -284,15 +284,16 @@ int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, lo
   // updates between leaves run on the GEMM kernel (1.7x faster than 256-row
   // leaves at nb = 256 and 512)
   constexpr int kChunk = 128;
+  // the inverses of every 16 x 16 diagonal block depend on L only: one launch
+  hipLaunchKernelGGL((diag_block_inverse_kernel<T>), dim3((unsigned)cdiv(m, 16)), dim3(64), 0, s,
+                     m, L, ldl, (T*)work);
+  LP_LAUNCH_CHECK();
   for (int r0 = 0; r0 < m; r0 += kChunk) {
     const int mc = min(kChunk, m - r0);
     const T* Lc = L + (long long)r0 * ldl + r0;
     T* Bc = B + (long long)r0 * ldb;
     const int nt = (int)cdiv(mc, 16);
-    T* Linv = (T*)work;
-    hipLaunchKernelGGL((diag_block_inverse_kernel<T>), dim3(nt), dim3(64), 0, s, mc, Lc, ldl,
-                       Linv);
-    LP_LAUNCH_CHECK();
+    const T* Linv = (const T*)work + (size_t)(r0 / 16) * 256;
     const dim3 grid((unsigned)cdiv(ncols, 64));
     bool done = false;
 #define LP_TRSM_CASE(NTV)                                                                     \

@@ -222,6 +222,10 @@ def bench_mixed(lp, inputs, torch, dev, n, nb, prec, shift, seed, R, nrhs, fp64_
         "effective_tflops": eff,
         "effective_over_fp64_peak": eff / PEAK_FP64_TFLOPS,
         "frac_lowp_peak": eff / PEAK_LOWP_TFLOPS[prec],
+        # the factorization alone (its 2/3 n^3 flops over its own time)
+        "factor_tflops": (2.0 / 3.0) * n ** 3 / (last["t_factor_ms"] * 1e-3) / 1e12,
+        "frac_lowp_peak_factor": (2.0 / 3.0) * n ** 3 / (last["t_factor_ms"] * 1e-3) / 1e12
+                                 / PEAK_LOWP_TFLOPS[prec],
         "iterations": last["iterations"], "converged": last["converged"],
         "gmres_corrections": last["gmres_corrections"], "gmres_steps": last["gmres_steps"],
         "fell_back": last["fell_back"], "scaled_residual": last["scaled_residual"],

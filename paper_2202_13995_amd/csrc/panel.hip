@@ -231,6 +231,31 @@ __global__ __launch_bounds__(256) void trsm_mfma_kernel(int m, int ncols, const 
   const int col = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + c16;
   const bool colok = col < ncols;
   const int nt = (m + 15) >> 4;
+  // the strictly lower 16 x 16 blocks of the leaf, L(q, r) for q > r, staged
+  // in LDS by the whole workgroup with one round trip (rows past m as zeros):
+  // the solve below then waits on LDS, not on memory, at every step
+  constexpr int kPairs = NT * (NT - 1) / 2;
+  __shared__ T Ls[kPairs > 0 ? kPairs : 1][16][17];
+  if constexpr (kPairs > 0) {
+    const int i = threadIdx.x >> 4, k = threadIdx.x & 15;
+    T v[kPairs];
+    int u = 0;
+#pragma unroll
+    for (int q = 1; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < q; ++r, ++u) {
+        const int row = 16 * q + i;
+        const bool ok = q < nt && row < m;
+        const T a = L[(long long)(ok ? row : 0) * ldl + (ok ? 16 * r + k : 0)];
+        v[u] = ok ? a : T(0);
+      }
+    u = 0;
+#pragma unroll
+    for (int q = 1; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < q; ++r, ++u) Ls[u][i][k] = v[u];
+    __syncthreads();
+  }
   acc_t X[NT];
 #pragma unroll
   for (int r = 0; r < NT; ++r) {
@@ -251,13 +276,9 @@ __global__ __launch_bounds__(256) void trsm_mfma_kernel(int m, int ncols, const 
 #pragma unroll
       for (int q = r + 1; q < NT; ++q) {
         if (q < nt) {
-          const int row = 16 * q + c16;
-          const T* lrow = L + (long long)row * ldl + 16 * r;
+          const int pq = q * (q - 1) / 2 + r;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const T a = (row < m) ? -lrow[M::kidx(g, t)] : T(0);
-            X[q] = M::mma(a, X[r][t], X[q]);
-          }
+          for (int t = 0; t < 4; ++t) X[q] = M::mma(-Ls[pq][c16][M::kidx(g, t)], X[r][t], X[q]);
         }
       }
     }
@@ -307,7 +328,6 @@ int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, lo
     LP_TRSM_CASE(2)
     LP_TRSM_CASE(4)
     LP_TRSM_CASE(8)
-    LP_TRSM_CASE(16)
 #undef LP_TRSM_CASE
     if (!done) return LP_ENOTSUP;
     const int rest = m - r0 - mc;

@@ -74,6 +74,31 @@ __global__ __launch_bounds__(256) void trsm_right_upper_kernel(int m, int w,
   const bool rowok = row < m;
   const int nt = (w + 15) >> 4;
   const long long rbase = (long long)(rowok ? row : 0) * ldb;
+  // the blocks above the diagonal, transposed: Ut[p(q, r)][i][k] =
+  // U[16 r + k][16 q + i] for q > r, staged in LDS by the whole workgroup with
+  // one round trip (coalesced along U's rows; entries past w as zeros)
+  constexpr int kPairs = NT * (NT - 1) / 2;
+  __shared__ T Ut[kPairs > 0 ? kPairs : 1][16][17];
+  if constexpr (kPairs > 0) {
+    const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
+    T v[kPairs];
+    int u = 0;
+#pragma unroll
+    for (int q = 1; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < q; ++r, ++u) {
+        const int ur = 16 * r + a, uc = 16 * q + b;
+        const bool ok = q < nt && ur < w && uc < w;
+        const T x = U[(long long)(ok ? ur : 0) * ldu + (ok ? uc : 0)];
+        v[u] = ok ? x : T(0);
+      }
+    u = 0;
+#pragma unroll
+    for (int q = 1; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < q; ++r, ++u) Ut[u][b][a] = v[u];
+    __syncthreads();
+  }
   acc_t X[NT];
 #pragma unroll
   for (int r = 0; r < NT; ++r) {
@@ -97,14 +122,9 @@ __global__ __launch_bounds__(256) void trsm_right_upper_kernel(int m, int w,
       for (int q = r + 1; q < NT; ++q) {
         if (q < nt) {
           // (U^T)_qr[i][k] = U[16 r + k][16 q + i]: lane c16 supplies i
-          const int colq = 16 * q + c16;
-          const bool qok = colq < w;
+          const int pq = q * (q - 1) / 2 + r;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int k = 16 * r + M::kidx(g, t);
-            const T u = U[(long long)k * ldu + (qok ? colq : 0)];
-            X[q] = M::mma(qok ? -u : T(0), X[r][t], X[q]);
-          }
+          for (int t = 0; t < 4; ++t) X[q] = M::mma(-Ut[pq][c16][M::kidx(g, t)], X[r][t], X[q]);
         }
       }
     }

@@ -68,6 +68,11 @@ int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, lo
 // gather list (dst, src) into plan; see panel.hip.
 size_t swap_plan_bytes(int nswaps);
 int launch_swap_plan(const int32_t* ipiv, int k1, int k2, void* plan, hipStream_t s);
+// Interchanges k1..k2-1 (k2 - k1 <= 1024) applied to columns [c0, c1) in one
+// launch, each workgroup building the plan itself.
+template <typename T>
+int launch_swap_fused(T* A, long long lda, int c0, int c1, const int32_t* ipiv, int k1, int k2,
+                      hipStream_t s);
 // Apply a plan to columns [c0, c1) and [c2, c3) of A.
 template <typename T>
 int launch_swap_apply(T* A, long long lda, int c0, int c1, int c2, int c3, int nswaps,

@@ -60,7 +60,7 @@ constexpr int kPlanRing = 4;
 
 struct FactorLayout {
   size_t barriers, n_barriers, slots, staging, keys0, keys1, plan_trail, plan_bytes, linv_trail,
-      linv_left, plan_panel, linv_panel, pack_a, pack_b, total;
+      linv_left, linv_panel, pack_a, pack_b, total;
 };
 
 bool packs_operands(int prec) { return prec == LP_BF16 || prec == LP_FP16; }
@@ -87,9 +87,7 @@ FactorLayout factor_layout(int n, int nb, int prec) {
   // block inverses of the no-pivot left-block solve (its own stream)
   L.linv_left = off;
   off = align_up(off + trsm_workspace_bytes(256), 256);
-  // the exchanges and block inverses inside a split panel (the panel's stream)
-  L.plan_panel = off;
-  off += L.plan_bytes;
+  // the block inverses inside a split panel (the panel's stream)
   L.linv_panel = off;
   off = align_up(off + trsm_workspace_bytes(kMaxNb / 2), 256);
   // bfloat16 / half: the packed operands of the trailing update (-L of the
@@ -143,16 +141,15 @@ struct Factor {
   // moves a quarter of that plus one rank-h product on the GEMM kernel.  The
   // pivots and the arithmetic of each element are those of partial pivoting;
   // only the grouping of the right half's updates changes.
-  int panel_split(int j0, int w, int max_wgs, void* plan, void* linv, int depth) {
+  int panel_split(int j0, int w, int max_wgs, void* linv, int depth) {
     const int h = (w / 64) * 32;
     auto half = [&](int c, int ww) -> int {
-      return (depth > 1 && ww >= 256) ? panel_split(c, ww, max_wgs, plan, linv, depth - 1)
+      return (depth > 1 && ww >= 256) ? panel_split(c, ww, max_wgs, linv, depth - 1)
                                       : panel(c, ww, max_wgs);
     };
     int rc = half(j0, h);
     if (rc != LP_OK) return rc;
-    if ((rc = launch_swap_plan(ipiv, j0, j0 + h, plan, s)) != LP_OK) return rc;
-    if ((rc = launch_swap_apply<T>(A, lda, j0 + h, j0 + w, 0, 0, h, plan, s)) != LP_OK)
+    if ((rc = launch_swap_fused<T>(A, lda, j0 + h, j0 + w, ipiv, j0, j0 + h, s)) != LP_OK)
       return rc;
     if ((rc = launch_trsm_lower_unit<T>(h, w - h, at(j0, j0), lda, at(j0, j0 + h), lda, linv,
                                         s)) != LP_OK)
@@ -162,8 +159,7 @@ struct Factor {
                                  lda, at(j0 + h, j0 + h), lda, s, kGemmPanel)) != LP_OK)
       return rc;
     if ((rc = half(j0 + h, w - h)) != LP_OK) return rc;
-    if ((rc = launch_swap_plan(ipiv, j0 + h, j0 + w, plan, s)) != LP_OK) return rc;
-    return launch_swap_apply<T>(A, lda, j0, j0 + h, 0, 0, w - h, plan, s);
+    return launch_swap_fused<T>(A, lda, j0, j0 + h, ipiv, j0 + h, j0 + w, s);
   }
 
   // the same columns without pivoting, as the paper's LU and left kernels:
@@ -442,8 +438,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
     if (!piv) return f.panel_nopiv(j0, w, linv_left, work + L.linv_panel, kNopivSplitDepth);
     if (split_rows > 0 && w >= 256 && n - j0 >= split_rows)
-      return f.panel_split(j0, w, max_wgs, work + L.plan_panel, work + L.linv_panel,
-                           kSplitDepth);
+      return f.panel_split(j0, w, max_wgs, work + L.linv_panel, kSplitDepth);
     return f.panel(j0, w, max_wgs);
   };
   char* plan_ring = work + L.plan_trail;

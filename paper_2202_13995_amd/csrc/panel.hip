@@ -167,6 +167,69 @@ int launch_swap_apply(T* A, long long lda, int c0, int c1, int c2, int c3, int n
   return LP_OK;
 }
 
+// The interchanges k1 .. k2-1 applied to columns [c0, c1) in one launch:
+// every workgroup builds the plan in LDS from ipiv (the same parallel
+// construction as swap_plan_kernel) and gathers its column chunk.  For the
+// narrow column ranges inside a split panel, where the separate plan launch
+// cost more than building it once per workgroup.
+template <typename T, int Q>
+__global__ __launch_bounds__(1024) void swap_fused_kernel(T* __restrict__ A, long long lda, int c0,
+                                                          int c1, int CW,
+                                                          const int32_t* __restrict__ ipiv,
+                                                          int k1, int k2) {
+  __shared__ int piv[kPlanMax];
+  __shared__ int nxt[kPlanMax];
+  __shared__ int Bv[kPlanMax];
+  __shared__ int flag[2 * kPlanMax];
+  __shared__ int dst[2 * kPlanMax];
+  __shared__ int src[2 * kPlanMax];
+  __shared__ int nent_s;
+  const int k = k2 - k1;
+  if ((int)threadIdx.x < k) piv[threadIdx.x] = ipiv[k1 + threadIdx.x];
+  __syncthreads();
+  build_swap_plan(piv, k1, k2, nxt, Bv, nullptr, flag, dst, src, &nent_s);
+  __syncthreads();
+  const int nent = nent_s;
+  const int cs = c0 + blockIdx.x * CW;
+  const int width = min(c1, cs + CW) - cs;
+  T v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 1024 * q;
+    const int ent = e / CW;
+    const int col = e - ent * CW;
+    if (ent < nent && col < width) v[q] = A[(long long)src[ent] * lda + cs + col];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 1024 * q;
+    const int ent = e / CW;
+    const int col = e - ent * CW;
+    if (ent < nent && col < width) A[(long long)dst[ent] * lda + cs + col] = v[q];
+  }
+}
+
+template <typename T>
+int launch_swap_fused(T* A, long long lda, int c0, int c1, const int32_t* ipiv, int k1, int k2,
+                      hipStream_t s) {
+  constexpr int Q = 16;
+  const int k = k2 - k1;
+  if (k <= 0 || c1 <= c0) return LP_OK;
+  if (k > kPlanMax) return LP_ENOTSUP;
+  int CW = 64;
+  while (CW > 1 && 2 * k * CW > 1024 * Q) CW >>= 1;
+  hipLaunchKernelGGL((swap_fused_kernel<T, Q>), dim3((unsigned)cdiv(c1 - c0, CW)), dim3(1024), 0,
+                     s, A, lda, c0, c1, CW, ipiv, k1, k2);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+template int launch_swap_fused<double>(double*, long long, int, int, const int32_t*, int, int,
+                                       hipStream_t);
+template int launch_swap_fused<float>(float*, long long, int, int, const int32_t*, int, int,
+                                      hipStream_t);
+
 template int launch_swap_apply<double>(double*, long long, int, int, int, int, int, const void*,
                                        hipStream_t);
 template int launch_swap_apply<float>(float*, long long, int, int, int, int, int, const void*,

@@ -239,11 +239,15 @@ template int launch_swap_apply<float>(float*, long long, int, int, int, int, int
 // B := L^-1 B, L unit lower m x m: the paper's "top blocks" update of the
 // blocks right of the diagonal block with its lower factor.
 //
-// Columns of B are independent.  One wave owns a strip of 16 columns and keeps
-// the whole strip (m <= 512 rows, as 16 x 16 tiles) in registers in the MFMA
-// output layout.  Block row r is solved by multiplying with the precomputed
-// inverse of the 16 x 16 diagonal block L_rr, then subtracted from every later
-// block row (X_q -= L_qr X_r), all on the matrix cores.  For both MFMA shapes
+// Columns of B are independent.  The triangle is taken in 128-row leaves, the
+// rows below each leaf brought up to date by the inner-block kernel between
+// leaf launches.  In a leaf launch one wave owns a strip of 16 columns and
+// keeps the strip's 128 rows (as 16 x 16 tiles) in registers in the MFMA
+// output layout, and the workgroup first stages the leaf's strictly lower
+// 16 x 16 blocks in LDS.  Block row r is solved by multiplying with the
+// precomputed inverse of the 16 x 16 diagonal block L_rr, then subtracted
+// from every later block row (X_q -= L_qr X_r), all on the matrix cores.  For
+// both MFMA shapes
 // used here there is an ordering of the 4-long k-steps for which output
 // register t of a lane is exactly that lane's B operand in k-step t, so solved
 // tiles feed the next products without leaving registers:

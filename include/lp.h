@@ -127,8 +127,8 @@ typedef struct {
                            at least this many rows are factored in two halves, the
                            right half updated by one product on the GEMM kernel
                            between them: 0 (default) every such panel of the bfloat16
-                           and half factorizations, none in binary64 and binary32;
-                           -1 never; k > 0 from k rows */
+                           and half factorizations, those of at most 8192 rows in
+                           binary64 and binary32; -1 never; k > 0 from k rows */
 } lp_factor_opts;
 
 typedef struct {

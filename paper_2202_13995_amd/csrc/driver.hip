@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -398,17 +399,25 @@ int lookahead_panel_wgs(int rows) {
   return std::max(sizeof(T) == 8 ? 48 : 128, (int)cdiv(rows, kPanelRowsPerWg));
 }
 
-// Panels split in halves by default: those of the bfloat16 / half
-// factorizations (-1: never).  Measured on one MI355X at n = 65536: there the
+// Panels split in halves by default (rows in [min_rows, max_rows]).  Measured
+// on one MI355X at n = 65536: in the bfloat16 / half factorizations the
 // trailing update is bound by memory traffic and the panel is the longer
 // chain, and the split gains at every size (nb = 512: 832 -> 800 ms; nb =
 // 1024: 861 -> 736 ms with halves split again, 770 ms without).  Where the
-// update is bound by the matrix cores the extra launches on the panel's
-// stream wait for compute units and lengthen its chain: binary64 3.17 s
-// unsplit against 3.30 s splitting only panels of 49152 rows or more and 3.48
-// s splitting all (n = 32768, nb = 256: 0.55 against 0.64 s); binary32 2.54
-// against 2.64 s.
-int default_split_rows(int prec) { return packs_operands(prec) ? 1 : -1; }
+// update is bound by the matrix cores, the extra launches on the panel's
+// stream wait for compute units beside it and lengthen its chain while the
+// update is long: binary64 3.17 s unsplit against 3.30 s splitting panels of
+// 49152 rows or more and 3.48 s splitting all (n = 32768, nb = 256: 0.55
+// against 0.64 s), binary32 2.54 against 2.64 s.  Short panels, which are
+// the longer chain at the end of the factorization, gain: splitting those of
+// at most 8192 rows took binary64 from 3.18 to 3.16 s (n = 32768: 0.534 to
+// 0.531 s; at most 16384 rows: 0.537 s) and binary32 from 2.58 to 2.57 s.
+struct SplitRule {
+  int min_rows, max_rows;
+};
+SplitRule default_split(int prec) {
+  return packs_operands(prec) ? SplitRule{1, INT_MAX} : SplitRule{1, 8192};
+}
 // halves of 256 columns or more are split again once (quarters of a 1024
 // panel: 736 ms; a third level 737-749 ms)
 constexpr int kSplitDepth = 2;
@@ -434,10 +443,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   void* linv_trail = work + L.linv_trail;
   void* linv_left = work + L.linv_left;
   const bool piv = cfg.pivot;
-  const int split_rows = cfg.split_rows != 0 ? cfg.split_rows : default_split_rows(prec);
+  const SplitRule split = cfg.split_rows == 0  ? default_split(prec)
+                          : cfg.split_rows > 0 ? SplitRule{cfg.split_rows, INT_MAX}
+                                               : SplitRule{INT_MAX, 0};
   auto factor_panel = [&](int j0, int w, int max_wgs) -> int {
     if (!piv) return f.panel_nopiv(j0, w, linv_left, work + L.linv_panel, kNopivSplitDepth);
-    if (split_rows > 0 && w >= 256 && n - j0 >= split_rows)
+    if (w >= 256 && n - j0 >= split.min_rows && n - j0 <= split.max_rows)
       return f.panel_split(j0, w, max_wgs, work + L.linv_panel, kSplitDepth);
     return f.panel(j0, w, max_wgs);
   };

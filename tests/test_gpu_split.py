@@ -1,6 +1,6 @@
 """GPU parity of the split panel (lp_factor_opts.panel_split_rows; by default
 the panels of the bfloat16 / half factorizations are split, binary64 and
-binary32 panels are not).  With partial pivoting (paper, section "High
+binary32 panels only when they have at most 8192 rows).  With partial pivoting (paper, section "High
 Performance Linpack"), a panel of 256 columns or more is factored as two
 halves, the right half brought up to date by one product on the GEMM kernel
 between them; only the grouping of the right half's updates changes, never a

@@ -98,11 +98,18 @@ def main():
     s = rnorm / (oracle.EPS * (anorm * xnorm + bnorm) * n)
     log(f"scaled residual {s:.4e}")
 
+    xv = np.ascontiguousarray(x.reshape(-1))
+    # the solution first: what follows must not lose hours of factorization
+    np.savez_compressed(base + ".npz", x=xv, ipiv=ipiv.astype(np.int32))
+    log(f"wrote {base}.npz")
+
     t0 = time.time()
     inv_norm = cond.inv_norm_inf_estimate(lu, ipiv)
     kappa = anorm * inv_norm
     log(f"kappa_inf estimate {kappa:.4e} ({time.time() - t0:.1f} s)")
-    del lu
+    # lu is a (factored in place): drop both before A is generated again, or
+    # two n x n arrays are alive at once (68.7 GB at n = 65536)
+    del lu, a
 
     # third solver: host LAPACK on A^T's column-major view (= A row-major),
     # solved with trans=1 so that it solves A x = b
@@ -116,8 +123,6 @@ def main():
     noise = float(np.abs(x_lapack - x).max() / np.abs(x).max())
     log(f"LAPACK noise floor {noise:.3e} ({t_lapack:.1f} s)")
 
-    xv = np.ascontiguousarray(x.reshape(-1))
-    np.savez_compressed(base + ".npz", x=xv, ipiv=ipiv.astype(np.int32))
     meta = {
         "what": "binary64 oracle solution of the synthetic LINPACK system "
                 "(A, b uniform[-0.5,0.5) from the seeded generator, unshifted)",

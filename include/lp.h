@@ -303,8 +303,9 @@ int lp_ir_decide(const double *h, int len, int corrections, int max_iter);
  * (lp_request_footprint).  Requests with n <= small_n_max are published into
  * a ring of up to max_batch descriptors in pinned host memory; a persistent
  * batched kernel of batch_workgroups workgroups pulls them, one workgroup per
- * request, each request completing on its own (for those the low-precision
- * route factors in binary32).  The kernel exits after 2 ms without requests
+ * request, each request completing on its own (factors held in the
+ * workgroup's LDS up to n = 128; for those the low-precision route factors in
+ * binary32).  The kernel exits after 2 ms without requests
  * and is launched again when one arrives.  Larger requests run the blocked
  * path on a worker thread and a stream of their own (large_slots at once;
  * 4 is a good value), their factorizations without look-ahead (no internal

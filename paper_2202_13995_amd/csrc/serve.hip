@@ -145,11 +145,11 @@ __device__ int wg_getrf(int n, T* W, int32_t* ipiv, int32_t* perm, double* rk, i
     }
     for (int i = k + 1 + threadIdx.x; i < n; i += kST) W[(long long)i * n + k] /= piv;
     __syncthreads();
-    const int m = n - k - 1;
-    for (long long e = threadIdx.x; e < (long long)m * m; e += kST) {
-      const int i = k + 1 + (int)(e / m);
-      const int j = k + 1 + (int)(e % m);
-      W[(long long)i * n + j] -= W[(long long)i * n + k] * W[(long long)k * n + j];
+    // rows over groups of 32 threads, columns over the threads of a group
+    for (int i = k + 1 + (int)(threadIdx.x >> 5); i < n; i += kST / 32) {
+      const T l = W[(long long)i * n + k];
+      for (int j = k + 1 + (int)(threadIdx.x & 31); j < n; j += 32)
+        W[(long long)i * n + j] -= l * W[(long long)k * n + j];
     }
     __syncthreads();
   }
@@ -241,7 +241,11 @@ __host__ __device__ inline size_t small_ws_bytes(int n, int nrhs, int prec) {
 // One request, by the whole workgroup; res[0..4] = {status, info, scaled
 // residual, iterations, fell_back} (res[5]: its device time, set by the caller).
 constexpr int kResWords = 6;
-__device__ void solve_small(const SmallReq& q, double* res, double* red, int* redi) {
+// Systems of at most kLdsN rows are factored and solved with their factors
+// held in the workgroup's LDS (128 KB for binary64), not in global memory.
+constexpr int kLdsN = 128;
+constexpr size_t kRingLdsBytes = sizeof(double) * kLdsN * kLdsN;
+__device__ void solve_small(const SmallReq& q, double* res, double* red, int* redi, void* lds) {
   const int n = q.n, nrhs = q.nrhs;
   char* w = (char*)q.W;
   const size_t el = (q.prec == LP_FP64) ? 8 : 4;
@@ -252,8 +256,9 @@ __device__ void solve_small(const SmallReq& q, double* res, double* red, int* re
   double status = 0.0, iters = 0.0, fell = 0.0, sres = 0.0;
   int info = 0;
   const double anorm = wg_anorm(n, q.A, q.lda, red);
+  const bool in_lds = n <= kLdsN;
   if (q.prec == LP_FP64) {
-    double* W = (double*)w;
+    double* W = in_lds ? (double*)lds : (double*)w;
     for (long long e = threadIdx.x; e < (long long)n * n; e += kST)
       W[e] = q.A[(e / n) * q.lda + e % n];
     __syncthreads();
@@ -269,7 +274,7 @@ __device__ void solve_small(const SmallReq& q, double* res, double* red, int* re
     }
   } else {
     // binary32 factors, binary64 refinement, binary64 fallback
-    float* W = (float*)w;
+    float* W = in_lds ? (float*)lds : (float*)w;
     double* Rv = (double*)(w + off);
     off = (off + 8 * (size_t)n * nrhs + 255) & ~(size_t)255;
     float* D = (float*)(w + off);
@@ -365,6 +370,7 @@ __global__ __launch_bounds__(kST) void ring_solve_kernel(const SmallReq* __restr
   __shared__ int redi[kST / 64];
   __shared__ long long s_job;
   __shared__ unsigned long long s_desc[(sizeof(SmallReq) + 7) / 8];
+  extern __shared__ __align__(16) unsigned char ring_lds[];  // kRingLdsBytes: small factors
   for (;;) {
     if (threadIdx.x == 0) {
       long long job = -1;
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(kST) void ring_solve_kernel(const SmallReq* __restr
     const SmallReq q = *reinterpret_cast<const SmallReq*>(s_desc);
     double res[kResWords];
     const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
-    solve_small(q, res, red, redi);
+    solve_small(q, res, red, redi, ring_lds);
     __syncthreads();
     if (threadIdx.x == 0) {
       const int slot = (int)(job % capacity);
@@ -842,7 +848,7 @@ static int ensure_ring_kernel(lp_server* sv) {
     if (q != hipSuccess) return LP_EHIP_BASE - (int)q;
   }
   const int wgs = std::max(1, std::min(sv->cfg.batch_workgroups, 4 * lp::num_cus()));
-  hipLaunchKernelGGL(lp::ring_solve_kernel, dim3(wgs), dim3(lp::kST), 0, rg.s,
+  hipLaunchKernelGGL(lp::ring_solve_kernel, dim3(wgs), dim3(lp::kST), lp::kRingLdsBytes, rg.s,
                      (const lp::SmallReq*)rg.desc, rg.results, rg.done,
                      (const lp::RingShared*)rg.shared, rg.head, rg.capacity);
   LP_LAUNCH_CHECK();

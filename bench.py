@@ -86,11 +86,24 @@ def cpu_baseline(n: int, seed: int) -> dict:
     lu, piv, info = oracle.getrf(a, overwrite=True)
     x = oracle.getrs(lu, piv, b)
     dt = time.perf_counter() - t0
-    return {"value": flops(n) / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
-            "kind": "oracle", "seconds": dt,
-            "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
-            "sample": f"one FP64 system n={n} (LU with partial pivoting + solve), "
-                      f"uniform[-0.5,0.5) seed {seed}; same operation count formula"}
+    out = {"value": flops(n) / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
+           "kind": "oracle", "seconds": dt,
+           "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
+           "sample": f"one FP64 system n={n} (LU with partial pivoting + solve), "
+                     f"uniform[-0.5,0.5) seed {seed}; same operation count formula"}
+    # the small configuration (n = 1024) on one thread and on all of them
+    small = {}
+    for t in (1, threads):
+        oracle.set_threads(t)
+        a = inputs.matrix(seed, 1024)
+        b = inputs.rhs(seed, 1024, 1)
+        t0 = time.perf_counter()
+        lu, piv, info = oracle.getrf(a, overwrite=True)
+        oracle.getrs(lu, piv, b)
+        small[f"threads_{t}_s"] = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out["n1024"] = small
+    return out
 
 
 def stats_ms(times_s) -> dict:

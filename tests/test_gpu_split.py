@@ -133,3 +133,18 @@ def test_split_panels_binary32(lp, n, nb, split):
     U = np.triu(got)
     pa = a32.astype(np.float64)[oracle.perm_from_ipiv(got_piv, n)]
     assert np.all(np.abs(pa - L @ U) <= 4 * n * 2.0 ** -24 * (np.abs(L) @ np.abs(U)))
+
+
+@pytest.mark.parametrize("zero_col", [40, 300, 450])
+def test_split_panels_first_zero_pivot(lp, zero_col):
+    """An exactly singular matrix (one zero column): the split and the single
+    launch report the oracle's first zero pivot (info = column + 1)."""
+    n, nb = 640, 256
+    A = inputs.matrix(23, n)
+    A[:, zero_col] = 0.0
+    _, _, info_o = oracle.getrf(A)
+    assert info_o == zero_col + 1
+    for split in (True, False):
+        tA = cuda(A)
+        _, info = lp.lu_factor(tA, nb, "fp64", split_rows=(1 if split else -1))
+        assert int(host(info)[0]) == info_o, split

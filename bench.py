@@ -607,7 +607,7 @@ def main() -> int:
     gemm_launches = sum(p["gemm_launches"] for p in profs)
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     phases = {k: sum(p[k] for p in profs) / K for k in
-              ("gemm_ms", "panel_ms", "swap_ms", "trsm_ms")}
+              ("gemm_ms", "panel_ms", "swap_ms", "trsm_ms", "swap_left_ms")}
     phases["gemm_launches_per_step"] = gemm_launches / K
     phases["gemm_avg_launch_us"] = 1e3 * gemm_ms / max(gemm_launches, 1)
     phases["gemm_avg_launch_gflop"] = gemm_flops / max(gemm_launches, 1) / 1e9

@@ -88,8 +88,10 @@ size_t lu_workspace_bytes(int n, int nb, int prec);
  *   work  device workspace of at least lu_workspace_bytes(n, nb, prec) bytes,
  *         8-byte aligned; its contents on entry do not matter.
  *   stream hipStream_t or NULL.
- * The call may create one internal stream and a few events for the
- * look-ahead and joins it back into `stream` before returning. */
+ * With look-ahead the call uses three internal streams and a few events from
+ * process-wide pools (the next panel; the exchanges and "top" solve of the
+ * columns right of the next panel; the exchanges left of the panel) and joins
+ * them back into `stream` before returning. */
 int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
               void *work, size_t work_bytes, void *stream);
 
@@ -138,10 +140,16 @@ typedef struct {
   double gemm_flops;    /* their algorithmic flops, 2 M N K per launch           */
   double gemm_bytes;    /* their algorithmic bytes: C read + write and operands  */
   double panel_ms;      /* summed device time of the panel factorizations        */
-  double swap_ms;       /* summed device time of the trailing row exchanges      */
+  double swap_ms;       /* summed device time of the row exchanges right of the
+                           panels (the ones the update waits for)                */
   double swap_bytes;    /* their algorithmic bytes (read + write of moved rows)  */
   double trsm_ms;       /* summed device time of the triangular solves           */
   double trsm_flops;    /* their algorithmic flops                               */
+  double swap_left_ms;  /* the same for the exchanges left of the panels: with
+                           look-ahead they run beside the update, on the compute
+                           units it leaves free, and nothing waits for them
+                           before the end                                        */
+  double swap_left_bytes;
 } lp_factor_profile;
 
 /* lu_factor with options (NULL = defaults) and an optional host profile.  When

@@ -63,7 +63,8 @@ class FactorProfile(ctypes.Structure):
                 ("gemm_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
                 ("gemm_bytes", ctypes.c_double), ("panel_ms", ctypes.c_double),
                 ("swap_ms", ctypes.c_double), ("swap_bytes", ctypes.c_double),
-                ("trsm_ms", ctypes.c_double), ("trsm_flops", ctypes.c_double)]
+                ("trsm_ms", ctypes.c_double), ("trsm_flops", ctypes.c_double),
+                ("swap_left_ms", ctypes.c_double), ("swap_left_bytes", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

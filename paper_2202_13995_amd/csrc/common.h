@@ -58,11 +58,16 @@ int launch_gemm_update_lp_packed(int prec, int M, int N, int K, const float* A, 
                                  const float* B, long long ldb, float* C, long long ldc,
                                  void* pa, void* pb, bool pack_a, hipStream_t s);
 
-// B := L^-1 B, L unit lower m x m (m <= 512); work: trsm_workspace_bytes(m).
+// B := L^-1 B, L unit lower m x m; work: trsm_workspace_bytes(m), which first
+// receives the inverses of L's 16 x 16 diagonal blocks.  With inverses_ready
+// the caller has already written them there (launch_diag_block_inverse, on a
+// stream ordered before this one), so several column ranges can share them.
 size_t trsm_workspace_bytes(int m);
 template <typename T>
+int launch_diag_block_inverse(int m, const T* L, long long ldl, void* work, hipStream_t s);
+template <typename T>
 int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
-                           void* work, hipStream_t s);
+                           void* work, hipStream_t s, bool inverses_ready = false);
 
 // Swap plan for interchanges k1..k2-1 (device ipiv, absolute rows): writes a
 // gather list (dst, src) into plan; see panel.hip.

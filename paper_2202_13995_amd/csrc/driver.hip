@@ -208,7 +208,7 @@ struct Prof {
     hipEvent_t a, b;
   };
   std::vector<Span> gemm, panel, swap, swapl, trsm;
-  double gemm_flops = 0, gemm_bytes = 0, swap_bytes = 0, trsm_flops = 0;
+  double gemm_flops = 0, gemm_bytes = 0, swap_bytes = 0, swapl_bytes = 0, trsm_flops = 0;
 
   int begin(std::vector<Span>& v, hipStream_t s) {
     if (!on) return LP_OK;
@@ -334,13 +334,14 @@ EventPool& timing_event_pool() {
 struct Lookahead {
   hipStream_t s2 = nullptr;  // the next panel
   hipStream_t s3 = nullptr;  // row exchanges left of the panel
+  hipStream_t s4 = nullptr;  // exchanges and "top" solve right of the next panel
   // once panels are short: the panel on reserved compute units (sp), the rest
   // of the step (sr) and the left exchanges (sr2) on the others
   hipStream_t sp = nullptr, sr = nullptr, sr2 = nullptr;
   std::vector<hipEvent_t> ev;
   ~Lookahead() {
     for (auto e : ev) event_pool().put(e);
-    for (hipStream_t x : {s2, s3})
+    for (hipStream_t x : {s2, s3, s4})
       if (x) stream_pool().put(x);
     for (hipStream_t x : {sp, sr, sr2})  // masked streams (optional mode): not pooled
       if (x) (void)hipStreamDestroy(x);
@@ -459,6 +460,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   if (cfg.lookahead && npanels > 1) {
     LP_HIP_TRY(stream_pool().get(&la.s2));
     LP_HIP_TRY(stream_pool().get(&la.s3));
+    LP_HIP_TRY(stream_pool().get(&la.s4));
   }
   // Optional reserved compute units for short panels.  While the trailing
   // update is long it hides the panel; once the panels are short they are the
@@ -478,6 +480,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   hipStream_t ms = s;      // the step's swaps, solve and update
   hipStream_t ps = la.s2;  // the next panel
   hipStream_t ls = la.s3;  // exchanges left of the panel
+  hipStream_t rs = la.s4;  // exchanges and "top" solve right of the next panel
   int pwgs = 0;            // workgroup cap of panel launches (0: whole chip)
   // per ring slot: the left exchanges that read it; the main stream waits for
   // it before writing the slot again
@@ -485,26 +488,37 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   const double es = sizeof(T);
   int packed_step = -1;  // the step whose -L is in the packed buffer
 
-  // trailing steps of panel k on the main stream over the column range [c0, c1)
-  // right of the panel (and, if left, the columns left of the panel)
-  auto trailing = [&](int j0, int w, int c0, int c1, bool left) -> int {
-    const int j1 = j0 + w;
+  // trailing steps of panel k over the column range [c0, c1) right of the
+  // panel (and, if left, the columns left of the panel): the row exchanges and
+  // the "top" solve on stream st (the solve with the block inverses already in
+  // linv_trail when inv_ready), then the update on the main stream
+  auto prepare = [&](int j0, int w, int c0, int c1, bool left, hipStream_t st,
+                     bool inv_ready) -> int {
     int r;
+    // The first span starts on the main stream, at the point the side stream
+    // waits for: an event recorded on the side stream just after its wait
+    // measured from far earlier than the work.
     if (piv) {
       if ((r = prof.begin(prof.swap, ms)) != LP_OK) return r;
-      if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, ms)) !=
+      if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, st)) !=
           LP_OK)
         return r;
-      if ((r = prof.end(prof.swap, ms)) != LP_OK) return r;
+      if ((r = prof.end(prof.swap, st)) != LP_OK) return r;
       prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
     }
     if (c1 <= c0) return LP_OK;
-    if ((r = prof.begin(prof.trsm, ms)) != LP_OK) return r;
+    if ((r = prof.begin(prof.trsm, piv ? st : ms)) != LP_OK) return r;
     if ((r = launch_trsm_lower_unit<T>(w, c1 - c0, f.at(j0, j0), lda, f.at(j0, c0), lda,
-                                       linv_trail, ms)) != LP_OK)
+                                       linv_trail, st, inv_ready)) != LP_OK)
       return r;
-    if ((r = prof.end(prof.trsm, ms)) != LP_OK) return r;
+    if ((r = prof.end(prof.trsm, st)) != LP_OK) return r;
     prof.trsm_flops += 1.0 * w * w * (c1 - c0);
+    return LP_OK;
+  };
+  auto update = [&](int j0, int w, int c0, int c1) -> int {
+    const int j1 = j0 + w;
+    int r;
+    if (c1 <= c0) return LP_OK;
     const int M = n - j1, N = c1 - c0;
     if (M <= 0) return LP_OK;
     if ((r = prof.begin(prof.gemm, ms)) != LP_OK) return r;
@@ -526,6 +540,10 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     prof.gemm_flops += 2.0 * M * N * w;
     prof.gemm_bytes += es * (2.0 * M * N + (double)M * w + (double)w * N);
     return LP_OK;
+  };
+  auto trailing = [&](int j0, int w, int c0, int c1, bool left) -> int {
+    const int r = prepare(j0, w, c0, c1, left, ms, false);
+    return r != LP_OK ? r : update(j0, w, c0, c1);
   };
 
   // panel 0 on the caller's stream
@@ -554,6 +572,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
         ms = la.sr;
         ps = la.sp;
         ls = la.sr2;
+        rs = nullptr;  // the main stream waited for its last work
         pwgs = reserve;
       }
     }
@@ -563,6 +582,23 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     if (left_done[slot]) LP_HIP_TRY(hipStreamWaitEvent(ms, left_done[slot], 0));
     if (piv && (j0 > 0 || j1 < n)) {
       if ((rc = launch_swap_plan(ipiv, j0, j1, plan_trail, ms)) != LP_OK) return rc;
+    }
+    // With look-ahead, the exchanges and the "top" solve of the columns right
+    // of the next panel run on their own stream, beside the same steps for
+    // the next panel's own columns and their update on the main stream; both
+    // ranges share one launch of L11's block inverses.
+    const bool side_rest = more && ps && rs && j1 + w2 < n;
+    hipEvent_t rest_ready = nullptr;
+    if (side_rest) {
+      if ((rc = launch_diag_block_inverse<T>(w, f.at(j0, j0), lda, linv_trail, ms)) != LP_OK)
+        return rc;
+      hipEvent_t inv_ready;
+      if ((rc = la.event(&inv_ready)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(inv_ready, ms));
+      LP_HIP_TRY(hipStreamWaitEvent(rs, inv_ready, 0));
+      if ((rc = prepare(j0, w, j1 + w2, n, false, rs, true)) != LP_OK) return rc;
+      if ((rc = la.event(&rest_ready)) != LP_OK) return rc;
+      LP_HIP_TRY(hipEventRecord(rest_ready, rs));
     }
     if (piv && ls && j0 > 0) {
       // the exchanges left of the panel: nothing reads those columns before the
@@ -574,13 +610,18 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       if ((rc = prof.begin(prof.swapl, ls)) != LP_OK) return rc;
       if ((rc = launch_swap_apply<T>(A, lda, 0, j0, 0, 0, w, plan_trail, ls)) != LP_OK) return rc;
       if ((rc = prof.end(prof.swapl, ls)) != LP_OK) return rc;
-      prof.swap_bytes += 2.0 * es * 2.0 * w * j0;
+      prof.swapl_bytes += 2.0 * es * 2.0 * w * j0;
       if ((rc = la.event(&left_done[slot])) != LP_OK) return rc;
       LP_HIP_TRY(hipEventRecord(left_done[slot], ls));
     }
     if (more && ps) {
       // the next panel's columns first, then factor it beside the rest
-      if ((rc = trailing(j0, w, j1, j1 + w2, false)) != LP_OK) return rc;
+      if (side_rest) {
+        if ((rc = prepare(j0, w, j1, j1 + w2, false, ms, true)) != LP_OK) return rc;
+        if ((rc = update(j0, w, j1, j1 + w2)) != LP_OK) return rc;
+      } else if ((rc = trailing(j0, w, j1, j1 + w2, false)) != LP_OK) {
+        return rc;
+      }
       hipEvent_t next_ready;
       if ((rc = la.event(&next_ready)) != LP_OK) return rc;
       LP_HIP_TRY(hipEventRecord(next_ready, ms));
@@ -593,7 +634,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       f.s = s;
       if ((rc = la.event(&panel_done)) != LP_OK) return rc;
       LP_HIP_TRY(hipEventRecord(panel_done, ps));
-      if ((rc = trailing(j0, w, j1 + w2, n, ls == nullptr)) != LP_OK) return rc;
+      if (side_rest) {
+        LP_HIP_TRY(hipStreamWaitEvent(ms, rest_ready, 0));
+        if ((rc = update(j0, w, j1 + w2, n)) != LP_OK) return rc;
+      } else if ((rc = trailing(j0, w, j1 + w2, n, ls == nullptr)) != LP_OK) {
+        return rc;
+      }
     } else {
       if ((rc = trailing(j0, w, j1, n, ls == nullptr)) != LP_OK) return rc;
       if (more) {
@@ -607,7 +653,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     }
   }
   // nothing may remain on the other streams past this point
-  for (hipStream_t side : {la.s2, la.s3, la.sp, la.sr, la.sr2}) {
+  for (hipStream_t side : {la.s2, la.s3, la.s4, la.sp, la.sr, la.sr2}) {
     if (!side) continue;
     hipEvent_t joined;
     if ((rc = la.event(&joined)) != LP_OK) return rc;
@@ -633,8 +679,10 @@ int factor_entry(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, in
     out->gemm_bytes = prof.gemm_bytes;
     out->panel_ms = Prof::total(prof.panel);
     out->panel_launches = (int)prof.panel.size();
-    out->swap_ms = Prof::total(prof.swap) + Prof::total(prof.swapl);
+    out->swap_ms = Prof::total(prof.swap);
     out->swap_bytes = prof.swap_bytes;
+    out->swap_left_ms = Prof::total(prof.swapl);
+    out->swap_left_bytes = prof.swapl_bytes;
     out->trsm_ms = Prof::total(prof.trsm);
     out->trsm_flops = prof.trsm_flops;
   }

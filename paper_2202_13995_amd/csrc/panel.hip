@@ -362,20 +362,31 @@ __global__ __launch_bounds__(256) void trsm_mfma_kernel(int m, int ncols, const 
 
 size_t trsm_workspace_bytes(int m) { return sizeof(double) * 256 * (size_t)cdiv(m, 16); }
 
-// Triangles taller than 256 rows: solve the first 256 rows, subtract their
+// The inverses of every 16 x 16 diagonal block of L depend on L only: one
+// launch for all of them.
+template <typename T>
+int launch_diag_block_inverse(int m, const T* L, long long ldl, void* work, hipStream_t s) {
+  if (m <= 0) return LP_OK;
+  hipLaunchKernelGGL((diag_block_inverse_kernel<T>), dim3((unsigned)cdiv(m, 16)), dim3(64), 0, s,
+                     m, L, ldl, (T*)work);
+  LP_LAUNCH_CHECK();
+  return LP_OK;
+}
+
+// Triangles taller than 128 rows: solve the first 128 rows, subtract their
 // contribution from the rows below with the inner-block update kernel, repeat.
 template <typename T>
 int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, long long ldb,
-                           void* work, hipStream_t s) {
+                           void* work, hipStream_t s, bool inverses_ready) {
   if (m <= 0 || ncols <= 0) return LP_OK;
   // 128-row leaves: a shorter dependency chain per wave than 256, and the
   // updates between leaves run on the GEMM kernel (1.7x faster than 256-row
   // leaves at nb = 256 and 512)
   constexpr int kChunk = 128;
-  // the inverses of every 16 x 16 diagonal block depend on L only: one launch
-  hipLaunchKernelGGL((diag_block_inverse_kernel<T>), dim3((unsigned)cdiv(m, 16)), dim3(64), 0, s,
-                     m, L, ldl, (T*)work);
-  LP_LAUNCH_CHECK();
+  if (!inverses_ready) {
+    const int rc = launch_diag_block_inverse<T>(m, L, ldl, work, s);
+    if (rc != LP_OK) return rc;
+  }
   for (int r0 = 0; r0 < m; r0 += kChunk) {
     const int mc = min(kChunk, m - r0);
     const T* Lc = L + (long long)r0 * ldl + r0;
@@ -408,9 +419,12 @@ int launch_trsm_lower_unit(int m, int ncols, const T* L, long long ldl, T* B, lo
   return LP_OK;
 }
 
+template int launch_diag_block_inverse<double>(int, const double*, long long, void*,
+                                               hipStream_t);
+template int launch_diag_block_inverse<float>(int, const float*, long long, void*, hipStream_t);
 template int launch_trsm_lower_unit<double>(int, int, const double*, long long, double*,
-                                            long long, void*, hipStream_t);
+                                            long long, void*, hipStream_t, bool);
 template int launch_trsm_lower_unit<float>(int, int, const float*, long long, float*, long long,
-                                           void*, hipStream_t);
+                                           void*, hipStream_t, bool);
 
 }  // namespace lp

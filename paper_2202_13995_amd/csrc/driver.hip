@@ -586,8 +586,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     // With look-ahead, the exchanges and the "top" solve of the columns right
     // of the next panel run on their own stream, beside the same steps for
     // the next panel's own columns and their update on the main stream; both
-    // ranges share one launch of L11's block inverses.
-    const bool side_rest = more && ps && rs && j1 + w2 < n;
+    // ranges share one launch of L11's block inverses.  Not in the bfloat16 /
+    // half factorizations: there the panel chain is the longer one for most
+    // steps, and the next panel's columns, which are on that chain, slowed
+    // down beside the rest's exchanges and solve (n = 65536, nb = 1024: 0.89
+    // -> 1.19 ms from the end of a panel to the start of the next).
+    const bool side_rest = more && ps && rs && j1 + w2 < n && !packs_operands(prec);
     hipEvent_t rest_ready = nullptr;
     if (side_rest) {
       if ((rc = launch_diag_block_inverse<T>(w, f.at(j0, j0), lda, linv_trail, ms)) != LP_OK)

@@ -495,11 +495,8 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   auto prepare = [&](int j0, int w, int c0, int c1, bool left, hipStream_t st,
                      bool inv_ready) -> int {
     int r;
-    // The first span starts on the main stream, at the point the side stream
-    // waits for: an event recorded on the side stream just after its wait
-    // measured from far earlier than the work.
     if (piv) {
-      if ((r = prof.begin(prof.swap, ms)) != LP_OK) return r;
+      if ((r = prof.begin(prof.swap, st)) != LP_OK) return r;
       if ((r = launch_swap_apply<T>(A, lda, c0, c1, 0, left ? j0 : 0, w, plan_trail, st)) !=
           LP_OK)
         return r;
@@ -507,7 +504,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
       prof.swap_bytes += 2.0 * es * 2.0 * w * ((c1 - c0) + (left ? j0 : 0));
     }
     if (c1 <= c0) return LP_OK;
-    if ((r = prof.begin(prof.trsm, piv ? st : ms)) != LP_OK) return r;
+    if ((r = prof.begin(prof.trsm, st)) != LP_OK) return r;
     if ((r = launch_trsm_lower_unit<T>(w, c1 - c0, f.at(j0, j0), lda, f.at(j0, c0), lda,
                                        linv_trail, st, inv_ready)) != LP_OK)
       return r;

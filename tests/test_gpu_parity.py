@@ -283,6 +283,47 @@ def test_factorization_is_deterministic(lp):
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("lookahead", [True, False])
+def test_factor_profile_accounts_every_step(lp, lookahead):
+    """lu_factor_ex's profile: the algorithmic counts follow from n and nb
+    alone (sum of 2 M N K over the trailing updates, w^2 N over the "top"
+    solves, 32 w N bytes of exchanges right and 32 w j0 left of each panel),
+    whichever streams ran the work, and the factors equal those of the same
+    call without a profile."""
+    n, nb = 4096 + 40, 256
+    A = inputs.matrix(17, n)
+    t0, t1 = cuda(A), cuda(A)
+    ipiv0, _ = lp.lu_factor(t0, nb, lookahead=lookahead)
+    ipiv1, info, prof = lp.lu_factor(t1, nb, lookahead=lookahead, profile=True)
+    assert int(host(info)[0]) == 0
+    assert np.array_equal(host(t0), host(t1)) and np.array_equal(host(ipiv0), host(ipiv1))
+    flops = trsm = right = left = 0.0
+    launches = 0
+    for j0 in range(0, n, nb):
+        w = min(nb, n - j0)
+        j1 = j0 + w
+        m = n - j1
+        flops += 2.0 * m * m * w
+        trsm += 1.0 * w * w * m
+        right += 32.0 * w * m
+        left += 32.0 * w * j0
+        if m > 0:
+            # with look-ahead the next panel's columns and the rest are two updates
+            launches += 1 + (1 if lookahead and m > min(nb, m) else 0)
+    assert prof["panel_launches"] == -(-n // nb)
+    assert prof["gemm_launches"] == launches
+    assert prof["gemm_flops"] == flops and prof["trsm_flops"] == trsm
+    if lookahead:
+        # left exchanges on their own stream, counted apart
+        assert prof["swap_bytes"] == right and prof["swap_left_bytes"] == left
+        assert prof["swap_left_ms"] > 0
+    else:
+        assert prof["swap_bytes"] == right + left and prof["swap_left_bytes"] == 0
+    for k in ("gemm_ms", "panel_ms", "swap_ms", "trsm_ms"):
+        assert prof[k] > 0, k
+    assert prof["gemm_ms"] < 1e4 and prof["swap_left_ms"] >= 0
+
+
 # ------------------------------------------------------------------ residual
 def test_residual_check_matches_oracle(lp):
     rng = np.random.default_rng(5)

@@ -14,7 +14,9 @@
 // phase of the next iteration overlaps the update phase), step 4 first updates
 // only the next panel's columns, the next panel is factored on a second stream
 // while the rest of the multiplication runs, and step 2/3 of the next
-// iteration wait for both.
+// iteration wait for both.  Steps 2/3 of the columns right of the next panel
+// run on a third stream beside those of the next panel's own columns
+// (binary64 / binary32), and step 2 left of the panel on a fourth.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -750,7 +750,7 @@ static int retire(lp_server* sv) {
 // decisions), so the poll loop keeps admitting and publishing other work.  A
 // failure is reported as a failed request (status 1), never stranded; the
 // request's memory returns to the pool at retirement either way.  The
-// factorizations run without look-ahead: its two internal streams per solve
+// factorizations run without look-ahead: its internal streams per solve
 // would multiply the streams sharing the device's few hardware queues, where
 // a kernel at the head of a queue holds up every stream behind it.
 static void run_large_fp64(lp_server::Large* l, const lp_request r, char* base,

@@ -88,10 +88,11 @@ size_t lu_workspace_bytes(int n, int nb, int prec);
  *   work  device workspace of at least lu_workspace_bytes(n, nb, prec) bytes,
  *         8-byte aligned; its contents on entry do not matter.
  *   stream hipStream_t or NULL.
- * With look-ahead the call uses three internal streams and a few events from
- * process-wide pools (the next panel; the exchanges and "top" solve of the
- * columns right of the next panel; the exchanges left of the panel) and joins
- * them back into `stream` before returning. */
+ * With look-ahead the call uses three internal streams (two for LP_BF16 and
+ * LP_FP16) and a few events from process-wide pools (the next panel; the
+ * exchanges and "top" solve of the columns right of the next panel, binary64
+ * and binary32 only; the exchanges left of the panel) and joins them back
+ * into `stream` before returning. */
 int lu_factor(int n, int nb, int prec, void *A, int lda, int32_t *ipiv, int32_t *info,
               void *work, size_t work_bytes, void *stream);
 

@@ -462,7 +462,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   if (cfg.lookahead && npanels > 1) {
     LP_HIP_TRY(stream_pool().get(&la.s2));
     LP_HIP_TRY(stream_pool().get(&la.s3));
-    LP_HIP_TRY(stream_pool().get(&la.s4));
+    if (!packs_operands(prec)) LP_HIP_TRY(stream_pool().get(&la.s4));
   }
   // Optional reserved compute units for short panels.  While the trailing
   // update is long it hides the panel; once the panels are short they are the
@@ -483,6 +483,7 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   hipStream_t ps = la.s2;  // the next panel
   hipStream_t ls = la.s3;  // exchanges left of the panel
   hipStream_t rs = la.s4;  // exchanges and "top" solve right of the next panel
+                           // (binary64 / binary32 only, see below)
   int pwgs = 0;            // workgroup cap of panel launches (0: whole chip)
   // per ring slot: the left exchanges that read it; the main stream waits for
   // it before writing the slot again
@@ -586,11 +587,12 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
     // of the next panel run on their own stream, beside the same steps for
     // the next panel's own columns and their update on the main stream; both
     // ranges share one launch of L11's block inverses.  Not in the bfloat16 /
-    // half factorizations: there the panel chain is the longer one for most
-    // steps, and the next panel's columns, which are on that chain, slowed
-    // down beside the rest's exchanges and solve (n = 65536, nb = 1024: 0.89
-    // -> 1.19 ms from the end of a panel to the start of the next).
-    const bool side_rest = more && ps && rs && j1 + w2 < n && !packs_operands(prec);
+    // half factorizations (rs is not taken for them): there the panel chain
+    // is the longer one for most steps, and the next panel's columns, which
+    // are on that chain, slowed down beside the rest's exchanges and solve
+    // (n = 65536, nb = 1024: 0.89 -> 1.19 ms from the end of a panel to the
+    // start of the next).
+    const bool side_rest = more && ps && rs && j1 + w2 < n;
     hipEvent_t rest_ready = nullptr;
     if (side_rest) {
       if ((rc = launch_diag_block_inverse<T>(w, f.at(j0, j0), lda, linv_trail, ms)) != LP_OK)

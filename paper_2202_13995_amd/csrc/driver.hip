@@ -491,10 +491,11 @@ int factor_impl(int n, int nb, int prec, T* A, long long lda, int32_t* ipiv, int
   const double es = sizeof(T);
   int packed_step = -1;  // the step whose -L is in the packed buffer
 
-  // trailing steps of panel k over the column range [c0, c1) right of the
-  // panel (and, if left, the columns left of the panel): the row exchanges and
-  // the "top" solve on stream st (the solve with the block inverses already in
-  // linv_trail when inv_ready), then the update on the main stream
+  // Trailing steps of panel k over the column range [c0, c1) right of the
+  // panel (and, if left, the columns left of the panel).  prepare: the row
+  // exchanges and the "top" solve on stream st (with the block inverses
+  // already in linv_trail when inv_ready); update: the multiplication on the
+  // main stream; trailing: both on the main stream.
   auto prepare = [&](int j0, int w, int c0, int c1, bool left, hipStream_t st,
                      bool inv_ready) -> int {
     int r;
